@@ -1,0 +1,325 @@
+/*
+ * CPU oracle for CONCORD-PCD.  TEST INFRASTRUCTURE ONLY: the tests, the smoke
+ * check and the benchmark's CPU-baseline leg load this library; the solver
+ * never does.  It shares no code with the HIP path.
+ *
+ * Plain, serial, double-precision restatement of the coordinate-descent
+ * methods of Choi, Lee & Yu, "An efficient parallel block coordinate descent
+ * algorithm for large-scale precision matrix estimation using graphics
+ * processing units" (arXiv 2106.09382):
+ *
+ *   - CONCORD-CD (Section 2.1): diagonals by eq. (2), then every off-diagonal
+ *     by eq. (3), one coordinate at a time, each using the latest values.
+ *   - CONCORD-PCD (Section 3, Algorithm 1): the off-diagonals are visited in
+ *     p_even - 1 parallel steps given by the circle-method round-robin table
+ *     (Section 3.2, steps i-iv); all pairs of a step are updated from the same
+ *     iterate; then all diagonals; then the convergence test.
+ *
+ * Scale: every routine takes S = X^T X / n instead of T = X^T X.  Dividing
+ * eqs. (2) and (3) by n gives the same updates with T -> S and the threshold
+ * lambda -> lambda / n, so the lambda passed here is the threshold on the S
+ * scale (the paper's lambda values 0.1 and 0.3 are on this scale).
+ *
+ * Numerators are direct sums over the current Omega, exactly as eqs. (2)-(3)
+ * write them; there is no maintained product and no reordering of terms.
+ *
+ * Omega is a dense, symmetric, row-major p x p array; an off-diagonal update
+ * writes both omega_ij and omega_ji.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* Soft_tau(x) = sign(x) (|x| - tau)_+  (Section 2.1, below eq. (3)).
+ * |x| == tau gives exactly zero. */
+static double soft(double x, double tau)
+{
+    double a = fabs(x) - tau;
+    if (a <= 0.0)
+        return 0.0;
+    return x > 0.0 ? a : -a;
+}
+
+/* Numerator of eq. (3) before the sign flip:
+ *   b_ij = sum_{u != j} omega_iu S_ju + sum_{u != i} omega_uj S_iu.
+ * Omega is symmetric, so omega_uj is read from row j. */
+static double offdiag_sum(const double *S, const double *om, int p, int i, int j)
+{
+    const double *oi = om + (size_t)i * p, *oj = om + (size_t)j * p;
+    const double *si = S + (size_t)i * p, *sj = S + (size_t)j * p;
+    double b1 = 0.0, b2 = 0.0;
+    for (int u = 0; u < j; ++u)
+        b1 += oi[u] * sj[u];
+    for (int u = j + 1; u < p; ++u)
+        b1 += oi[u] * sj[u];
+    for (int u = 0; u < i; ++u)
+        b2 += oj[u] * si[u];
+    for (int u = i + 1; u < p; ++u)
+        b2 += oj[u] * si[u];
+    return b1 + b2;
+}
+
+/* Eq. (3): omega_ij <- Soft_lambda(-b_ij) / (S_ii + S_jj). */
+static double offdiag_new(const double *S, const double *om, int p, int i, int j, double lam)
+{
+    double b = offdiag_sum(S, om, p, i, j);
+    return soft(-b, lam) / (S[(size_t)i * p + i] + S[(size_t)j * p + j]);
+}
+
+/* Eq. (2): with c = sum_{j != i} omega_ij S_ij,
+ *   omega_ii <- (-c + sqrt(c^2 + 4 S_ii)) / (2 S_ii).
+ * (T -> S turns 4 n T_ii into 4 S_ii after dividing by n^2 under the root.) */
+static double diag_new(const double *S, const double *om, int p, int i)
+{
+    const double *oi = om + (size_t)i * p, *si = S + (size_t)i * p;
+    double c = 0.0;
+    for (int u = 0; u < i; ++u)
+        c += oi[u] * si[u];
+    for (int u = i + 1; u < p; ++u)
+        c += oi[u] * si[u];
+    double sii = si[i];
+    return (-c + sqrt(c * c + 4.0 * sii)) / (2.0 * sii);
+}
+
+static int check_inputs(const double *S, int p, double lam, double tol, int maxit)
+{
+    if (!S || p < 1 || !(lam >= 0.0) || !(tol > 0.0) || maxit < 1)
+        return -1;
+    for (int i = 0; i < p; ++i)
+        if (!(S[(size_t)i * p + i] > 0.0))
+            return -3;
+    return 0;
+}
+
+static void start_point(double *om, const double *omega0, int p)
+{
+    if (omega0) {
+        memcpy(om, omega0, sizeof(double) * (size_t)p * p);
+    } else {
+        memset(om, 0, sizeof(double) * (size_t)p * p);
+        for (int i = 0; i < p; ++i)
+            om[(size_t)i * p + i] = 1.0;
+    }
+}
+
+static long long count_upper(const double *om, int p)
+{
+    long long k = 0;
+    for (int i = 0; i < p; ++i)
+        for (int j = i + 1; j < p; ++j)
+            k += om[(size_t)i * p + j] != 0.0;
+    return k;
+}
+
+/* Exported single-coordinate updates, for spot checks of a solution. */
+double oracle_offdiag_update(const double *S, const double *om, int p, int i, int j, double lam)
+{
+    return offdiag_new(S, om, p, i, j, lam);
+}
+
+double oracle_diag_update(const double *S, const double *om, int p, int i)
+{
+    return diag_new(S, om, p, i);
+}
+
+/*
+ * Round-robin table of Section 3.2 / Algorithm 1, written out literally.
+ * The index vector (j_1..j_pe) starts as (1..pe); step k's target set pairs
+ * position q with position pe - q + 1; after each step, j_pe moves to
+ * position 2 and positions 2..pe-1 shift right by one (position 1 is fixed).
+ *
+ * Output: pairs[(k * H + q) * 2 + {0,1}] for step k in [0, pe-1), slot q in
+ * [0, pe/2), as 0-based vertex numbers.  For odd p the value p is the
+ * paper's dummy index p+1 (a pair holding it is discarded, step iii).
+ * Returns the number of steps, or -1 for p < 1.
+ */
+int oracle_round_robin(int p, int32_t *pairs)
+{
+    if (p < 1)
+        return -1;
+    int pe = p + (p & 1), H = pe / 2, m = pe - 1;
+    int *jv = (int *)malloc(sizeof(int) * pe);
+    for (int s = 0; s < pe; ++s)
+        jv[s] = s + 1;
+    for (int k = 0; k < m; ++k) {
+        for (int q = 0; q < H; ++q) {
+            pairs[((size_t)k * H + q) * 2 + 0] = jv[q] - 1;
+            pairs[((size_t)k * H + q) * 2 + 1] = jv[pe - 1 - q] - 1;
+        }
+        int tmp = jv[pe - 1];
+        for (int s = pe - 1; s >= 2; --s)
+            jv[s] = jv[s - 1];
+        if (pe >= 2)
+            jv[1] = tmp;
+    }
+    free(jv);
+    return m;
+}
+
+/*
+ * CONCORD-PCD, Algorithm 1.
+ *
+ *   S       p x p sample Gram matrix X^T X / n (symmetric, S_ii > 0)
+ *   lam     threshold on the S scale
+ *   tol     stop when delta < tol, delta = max |change| over all entries of
+ *           the sweep (diagonal included), i.e. |Omega^(t) - Omega^(t-1)|_inf
+ *   maxit   sweep limit
+ *   omega0  start point (p x p) or NULL for the identity
+ *   omega   out, p x p
+ *   colour_limit  if > 0, stop after that many parallel off-diagonal steps in
+ *           total (possibly mid-sweep, before that sweep's diagonal step); used
+ *           to time a bounded sample and to watch the objective step by step
+ *   serial  0: each step computes all its new values from the same iterate
+ *           and then writes them (the parallel step of Algorithm 1);
+ *           1: writes each pair as soon as it is computed, in slot order
+ *   delta_trace  optional, maxit entries: delta of each sweep
+ *   info    out [0] sweeps, [1] last delta, [2] converged (1/0),
+ *           [3] nonzeros above the diagonal, [4] parallel steps done
+ *
+ * Returns 0 on success, -1 on invalid arguments, -3 when some S_ii <= 0.
+ */
+int oracle_pcd(const double *S, int p, double lam, double tol, int maxit,
+               const double *omega0, double *omega, long long colour_limit,
+               int serial, double *delta_trace, double *info)
+{
+    int rc = check_inputs(S, p, lam, tol, maxit);
+    if (rc)
+        return rc;
+    int pe = p + (p & 1), H = pe / 2, m = pe - 1;
+    int32_t *tab = (int32_t *)malloc(sizeof(int32_t) * (size_t)m * H * 2 + 8);
+    double *nv = (double *)malloc(sizeof(double) * (H + 1));
+    double *od = (double *)malloc(sizeof(double) * p);
+    start_point(omega, omega0, p);
+    oracle_round_robin(p, tab);
+
+    int t = 0, converged = 0;
+    double delta = 0.0;
+    long long steps = 0;
+    int stopped = 0;
+    while (!stopped && t < maxit) {
+        ++t;
+        delta = 0.0;
+        for (int k = 0; k < m; ++k) {
+            const int32_t *pr = tab + (size_t)k * H * 2;
+            if (serial) {
+                for (int q = 0; q < H; ++q) {
+                    int a = pr[2 * q], b = pr[2 * q + 1];
+                    if (a == p || b == p)
+                        continue;
+                    double w = offdiag_new(S, omega, p, a, b, lam);
+                    double d = fabs(w - omega[(size_t)a * p + b]);
+                    if (d > delta)
+                        delta = d;
+                    omega[(size_t)a * p + b] = w;
+                    omega[(size_t)b * p + a] = w;
+                }
+            } else {
+                for (int q = 0; q < H; ++q) {
+                    int a = pr[2 * q], b = pr[2 * q + 1];
+                    nv[q] = (a == p || b == p) ? 0.0 : offdiag_new(S, omega, p, a, b, lam);
+                }
+                for (int q = 0; q < H; ++q) {
+                    int a = pr[2 * q], b = pr[2 * q + 1];
+                    if (a == p || b == p)
+                        continue;
+                    double d = fabs(nv[q] - omega[(size_t)a * p + b]);
+                    if (d > delta)
+                        delta = d;
+                    omega[(size_t)a * p + b] = nv[q];
+                    omega[(size_t)b * p + a] = nv[q];
+                }
+            }
+            ++steps;
+            if (colour_limit > 0 && steps >= colour_limit) {
+                stopped = 1;
+                break;
+            }
+        }
+        if (stopped)
+            break;
+        /* Diagonal step: every c_i is taken from the post-step Omega; the
+         * diagonals do not enter one another's update, so one pass suffices. */
+        for (int i = 0; i < p; ++i)
+            od[i] = diag_new(S, omega, p, i);
+        for (int i = 0; i < p; ++i) {
+            double d = fabs(od[i] - omega[(size_t)i * p + i]);
+            if (d > delta)
+                delta = d;
+            omega[(size_t)i * p + i] = od[i];
+        }
+        if (delta_trace)
+            delta_trace[t - 1] = delta;
+        if (delta < tol) {
+            converged = 1;
+            break;
+        }
+    }
+    if (info) {
+        info[0] = t;
+        info[1] = delta;
+        info[2] = converged;
+        info[3] = (double)count_upper(omega, p);
+        info[4] = (double)steps;
+    }
+    free(tab);
+    free(nv);
+    free(od);
+    return 0;
+}
+
+/*
+ * CONCORD-CD (Section 2.1): each sweep updates the p diagonals by eq. (2),
+ * then the p(p-1)/2 off-diagonals by eq. (3) in lexicographic order
+ * (1,2), (1,3), ..., (p-1,p); every update uses the latest values.
+ * Arguments and return codes as for oracle_pcd (no colour limit; info[4] is
+ * the number of single-coordinate updates done).
+ */
+int oracle_cd(const double *S, int p, double lam, double tol, int maxit,
+              const double *omega0, double *omega, double *delta_trace, double *info)
+{
+    int rc = check_inputs(S, p, lam, tol, maxit);
+    if (rc)
+        return rc;
+    start_point(omega, omega0, p);
+    int t = 0, converged = 0;
+    double delta = 0.0;
+    long long updates = 0;
+    while (t < maxit) {
+        ++t;
+        delta = 0.0;
+        for (int i = 0; i < p; ++i) {
+            double w = diag_new(S, omega, p, i);
+            double d = fabs(w - omega[(size_t)i * p + i]);
+            if (d > delta)
+                delta = d;
+            omega[(size_t)i * p + i] = w;
+            ++updates;
+        }
+        for (int i = 0; i < p; ++i) {
+            for (int j = i + 1; j < p; ++j) {
+                double w = offdiag_new(S, omega, p, i, j, lam);
+                double d = fabs(w - omega[(size_t)i * p + j]);
+                if (d > delta)
+                    delta = d;
+                omega[(size_t)i * p + j] = w;
+                omega[(size_t)j * p + i] = w;
+                ++updates;
+            }
+        }
+        if (delta_trace)
+            delta_trace[t - 1] = delta;
+        if (delta < tol) {
+            converged = 1;
+            break;
+        }
+    }
+    if (info) {
+        info[0] = t;
+        info[1] = delta;
+        info[2] = converged;
+        info[3] = (double)count_upper(omega, p);
+        info[4] = (double)updates;
+    }
+    return 0;
+}
