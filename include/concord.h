@@ -1,0 +1,135 @@
+/*
+ * concord.h -- C ABI of the MI355X CONCORD-PCD solver.
+ *
+ * Solves the CONCORD problem (Choi, Lee & Yu, arXiv 2106.09382, Section 2.1,
+ * eq. (1)) by the edge-coloured parallel coordinate descent of Algorithm 1
+ * (Section 3): each sweep runs the p_even - 1 colour classes of the
+ * circle-method 1-factorisation of K_p (Section 3.2), updating all pairs of a
+ * class at once by eq. (3), then all diagonals by eq. (2), then the test
+ * |Omega^(t) - Omega^(t-1)|_inf < tol.
+ *
+ * Scale convention: the library works on S = X^T X / n (not T = X^T X) and
+ * `lambda` is the soft-threshold on that scale, i.e. the paper's updates with
+ * T = nS and threshold n*lambda.  The objective minimised is
+ *   F(Omega) = -sum_i log omega_ii + 1/2 tr(Omega S Omega) + lambda sum_{i<j} |omega_ij|.
+ *
+ * Conventions shared by every entry point:
+ *  - Matrices are dense, row-major, contiguous, in device memory of the
+ *    current HIP device, with element type given by `dt`.  Symmetric inputs
+ *    are used as given (no symmetrisation, no check).
+ *  - The caller owns all input and output buffers.  The library allocates its
+ *    workspace stream-ordered on `stream` and releases it before returning.
+ *  - Calls are stream-ordered and return after the work on `stream` has
+ *    completed, so host-side outputs (`info`) are valid on return.  `stream`
+ *    NULL means the default stream.  Calls on distinct streams may run
+ *    concurrently.
+ *  - Errors are returned as codes (never thrown).  On a negative code the
+ *    outputs are unspecified; CONCORD_NOT_CONVERGED still returns the last
+ *    iterate.
+ */
+#ifndef CONCORD_H
+#define CONCORD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { CONCORD_F32 = 0, CONCORD_F64 = 1 } concord_dtype;
+typedef enum { CONCORD_INPUT_S = 0, CONCORD_INPUT_Y = 1 } concord_input;
+
+enum {
+    CONCORD_OK = 0,
+    CONCORD_NOT_CONVERGED = 1, /* maxit sweeps done; Omega is the last iterate */
+    CONCORD_EINVAL = -1,       /* bad argument (sizes, pointers, lambda, tol, maxit, dtype) */
+    CONCORD_ENONFINITE = -2,   /* S (or Y) holds NaN/Inf, or the iteration left the finite range */
+    CONCORD_ENOTPD = -3,       /* some S_ii <= 0: eq. (2) and eq. (3) divide by S_ii */
+    CONCORD_ENOMEM = -4,       /* workspace allocation failed */
+    CONCORD_EDEVICE = -5,      /* HIP runtime error, or a device wait ran past its bound */
+    CONCORD_ELAUNCH = -6       /* launch shape cannot be made co-resident on this device */
+};
+
+/* Result of one solve. */
+typedef struct {
+    int32_t sweeps;     /* outer iterations t performed (the sweep that met the test counts) */
+    int32_t status;     /* CONCORD_OK or CONCORD_NOT_CONVERGED, or a negative code */
+    double delta;       /* |Omega^(t) - Omega^(t-1)|_inf of the last sweep, diagonal included */
+    double tol_eff;     /* tolerance applied: tol in FP64; max(tol, 16 eps_f32 max_i omega_ii) in FP32 */
+    int64_t nnz_upper;  /* #{i < j : omega_ij != 0} */
+    double objective;   /* F(Omega) at the returned Omega (from the maintained product) */
+    double elapsed_ms;  /* device time of the call (Gram, set-up, sweeps, output) */
+    double gram_ms;     /* device time of the Gram kernel (CONCORD_INPUT_Y), else 0 */
+    double sweep_ms;    /* device time of the persistent sweep kernel (all sweeps) */
+    int64_t moved_pairs;/* sum over sweeps of the number of pairs i<j whose omega_ij changed */
+    int64_t moved_diag; /* sum over sweeps of the number of diagonals that changed */
+    int32_t row_groups; /* launch shape used: workgroups sharing out the rows of W */
+    int32_t col_slices; /*   ... and the columns */
+    int32_t w_in_lds;   /*   1 if W blocks were held in LDS */
+    int32_t block_threads;
+} concord_info;
+
+/* Launch/tuning options; zero-initialise for defaults. */
+typedef struct {
+    int32_t row_groups;     /* workgroups sharing out the rows of W (0 = auto) */
+    int32_t col_slices;     /* workgroups sharing out the columns of W (0 = auto) */
+    int32_t block_threads;  /* threads per workgroup, multiple of 64 (0 = auto) */
+    int32_t w_in_lds;       /* -1/0 = auto, 1 = force W blocks in LDS, 2 = force W in HBM */
+    double *delta_trace;    /* optional host array of maxit entries: delta of every sweep */
+} concord_options;
+
+/*
+ * concord_fit -- one CONCORD-PCD solve (Algorithm 1).
+ *   kind    CONCORD_INPUT_S: X is S, p x p symmetric with S_ii > 0.
+ *           CONCORD_INPUT_Y: X is the n x p data matrix Y; the library forms
+ *           S = Y^T Y / n on the device (no centring or scaling).
+ *   n       rows of Y (ignored for CONCORD_INPUT_S)
+ *   p       number of variables, >= 1 (p_even = p + (p mod 2), p_even - 1 colours)
+ *   lambda  soft-threshold on the S scale, finite, >= 0
+ *   tol     stop when delta < tol (strict), tol > 0
+ *   maxit   sweep limit, >= 1
+ *   dt      element type of X, omega0 and omega; the iteration runs in it
+ *   omega0  start point, p x p symmetric with positive diagonal, or NULL for
+ *           the identity (Algorithm 1's Omega^(0))
+ *   omega   out, p x p; both triangles written (identical)
+ *   info    out (host pointer, may be NULL)
+ *   stream  hipStream_t or NULL
+ * Returns CONCORD_OK, CONCORD_NOT_CONVERGED or a negative code.
+ */
+int concord_fit(concord_input kind, const void *X, int64_t n, int64_t p, double lambda,
+                double tol, int32_t maxit, concord_dtype dt, const void *omega0, void *omega,
+                concord_info *info, void *stream);
+
+/* concord_fit with explicit launch options (opts may be NULL = defaults). */
+int concord_fit_ex(concord_input kind, const void *X, int64_t n, int64_t p, double lambda,
+                   double tol, int32_t maxit, concord_dtype dt, const void *omega0, void *omega,
+                   concord_info *info, void *stream, const concord_options *opts);
+
+/*
+ * concord_gram -- S = Y^T Y / n (the T = X^T X of Algorithm 1's set-up, on
+ * the S scale), computed with matrix-core (MFMA) instructions.
+ *   Y  n x p device matrix, S  p x p device output (both triangles written).
+ */
+int concord_gram(const void *Y, int64_t n, int64_t p, concord_dtype dt, void *S, void *stream);
+
+/*
+ * concord_schedule -- host-side closed form of the round-robin table of
+ * Section 3.2 (the target sets I_k of Algorithm 1).  Writes
+ * pairs[(k * (p_even/2) + q) * 2 + {0,1}] = 0-based vertices of slot q of
+ * colour k, for k < p_even - 1; the value p marks the dummy vertex of odd p
+ * (the paper's index p+1; such a slot is idle).  `pairs` is a host buffer of
+ * (p_even - 1) * p_even entries.  Returns the number of colours or CONCORD_EINVAL.
+ */
+int64_t concord_schedule(int64_t p, int32_t *pairs);
+
+/* Static description of a code. */
+const char *concord_strerror(int code);
+
+/* Library version string. */
+const char *concord_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CONCORD_H */

@@ -1,0 +1,210 @@
+"""ctypes binding of libconcord.so (argument marshalling only).
+
+Every step of a solve runs in the library's HIP kernels; this module only
+turns torch tensors into device pointers and the status codes into Python
+exceptions.  torch is imported first so that the library binds to the HIP
+runtime torch has already loaded (one runtime per process).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import warnings
+
+import torch  # noqa: F401  (must be loaded before libconcord.so)
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libconcord.so")
+
+F32, F64 = 0, 1
+INPUT_S, INPUT_Y = 0, 1
+OK, NOT_CONVERGED = 0, 1
+EINVAL, ENONFINITE, ENOTPD, ENOMEM, EDEVICE, ELAUNCH = -1, -2, -3, -4, -5, -6
+
+
+class ConcordInfo(ctypes.Structure):
+    _fields_ = [
+        ("sweeps", ctypes.c_int32),
+        ("status", ctypes.c_int32),
+        ("delta", ctypes.c_double),
+        ("tol_eff", ctypes.c_double),
+        ("nnz_upper", ctypes.c_int64),
+        ("objective", ctypes.c_double),
+        ("elapsed_ms", ctypes.c_double),
+        ("gram_ms", ctypes.c_double),
+        ("sweep_ms", ctypes.c_double),
+        ("moved_pairs", ctypes.c_int64),
+        ("moved_diag", ctypes.c_int64),
+        ("row_groups", ctypes.c_int32),
+        ("col_slices", ctypes.c_int32),
+        ("w_in_lds", ctypes.c_int32),
+        ("block_threads", ctypes.c_int32),
+    ]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ConcordOptions(ctypes.Structure):
+    _fields_ = [
+        ("row_groups", ctypes.c_int32),
+        ("col_slices", ctypes.c_int32),
+        ("block_threads", ctypes.c_int32),
+        ("w_in_lds", ctypes.c_int32),
+        ("delta_trace", ctypes.POINTER(ctypes.c_double)),
+    ]
+
+
+class ConcordError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"concord error {code}: {msg}")
+        self.code = code
+
+
+class NotConvergedWarning(UserWarning):
+    pass
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the built library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(
+            f"{path} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'` "
+            "(there is no CPU fallback)")
+    lib = ctypes.CDLL(path)
+    vp, i64, i32, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+    lib.concord_fit.argtypes = [ctypes.c_int, vp, i64, i64, dbl, dbl, i32, ctypes.c_int, vp, vp,
+                                ctypes.POINTER(ConcordInfo), vp]
+    lib.concord_fit.restype = ctypes.c_int
+    lib.concord_fit_ex.argtypes = lib.concord_fit.argtypes + [ctypes.POINTER(ConcordOptions)]
+    lib.concord_fit_ex.restype = ctypes.c_int
+    lib.concord_gram.argtypes = [vp, i64, i64, ctypes.c_int, vp, vp]
+    lib.concord_gram.restype = ctypes.c_int
+    lib.concord_schedule.argtypes = [i64, ctypes.POINTER(ctypes.c_int32)]
+    lib.concord_schedule.restype = i64
+    lib.concord_strerror.argtypes = [ctypes.c_int]
+    lib.concord_strerror.restype = ctypes.c_char_p
+    lib.concord_version.argtypes = []
+    lib.concord_version.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def strerror(code: int) -> str:
+    return load().concord_strerror(int(code)).decode()
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    if t.dtype == torch.float64:
+        return F64
+    if t.dtype == torch.float32:
+        return F32
+    raise TypeError(f"unsupported dtype {t.dtype}; use float32 or float64")
+
+
+def _check_dev(t: torch.Tensor, name: str):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def _stream_handle(stream) -> ctypes.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _raise(code: int, what: str):
+    if code < 0:
+        raise ConcordError(code, f"{what}: {strerror(code)}")
+    if code == NOT_CONVERGED:
+        warnings.warn(f"{what}: {strerror(code)}", NotConvergedWarning, stacklevel=3)
+
+
+def fit(X: torch.Tensor, lam: float, tol: float = 1e-6, maxit: int = 500, *, kind: str = "S",
+        omega0: torch.Tensor | None = None, out: torch.Tensor | None = None, stream=None,
+        row_groups: int = 0, col_slices: int = 0, block_threads: int = 0, w_in_lds: int = 0,
+        trace: bool = False, check: bool = True):
+    """One CONCORD-PCD solve.  X is S (p x p) or, with kind='Y', Y (n x p).
+
+    Returns (omega, info dict); info['delta_trace'] holds every sweep's delta
+    when ``trace`` is set.  Raises ConcordError on a negative status (unless
+    check=False) and warns when the sweep limit was reached.
+    """
+    lib = load()
+    _check_dev(X, "X")
+    dt = _dtype_code(X)
+    if kind == "S":
+        if X.dim() != 2 or X.shape[0] != X.shape[1]:
+            raise ValueError("S must be square")
+        p, n, kc = X.shape[0], 0, INPUT_S
+    elif kind == "Y":
+        if X.dim() != 2:
+            raise ValueError("Y must be a matrix")
+        n, p, kc = X.shape[0], X.shape[1], INPUT_Y
+    else:
+        raise ValueError("kind must be 'S' or 'Y'")
+    if out is None:
+        out = torch.empty((p, p), dtype=X.dtype, device=X.device)
+    _check_dev(out, "out")
+    if out.dtype != X.dtype or tuple(out.shape) != (p, p):
+        raise ValueError("out must be p x p with X's dtype")
+    o0 = None
+    if omega0 is not None:
+        _check_dev(omega0, "omega0")
+        if omega0.dtype != X.dtype or tuple(omega0.shape) != (p, p):
+            raise ValueError("omega0 must be p x p with X's dtype")
+        o0 = ctypes.c_void_p(omega0.data_ptr())
+    info = ConcordInfo()
+    opts = ConcordOptions(row_groups, col_slices, block_threads, w_in_lds, None)
+    tr = None
+    if trace:
+        tr = (ctypes.c_double * int(maxit))()
+        opts.delta_trace = ctypes.cast(tr, ctypes.POINTER(ctypes.c_double))
+    with torch.cuda.device(X.device):
+        code = lib.concord_fit_ex(kc, ctypes.c_void_p(X.data_ptr()), n, p, float(lam), float(tol),
+                                  int(maxit), dt, o0, ctypes.c_void_p(out.data_ptr()),
+                                  ctypes.byref(info), _stream_handle(stream), ctypes.byref(opts))
+    d = info.as_dict()
+    d["code"] = code
+    if tr is not None:
+        d["delta_trace"] = [tr[k] for k in range(max(0, info.sweeps))]
+    if check:
+        _raise(code, "concord_fit")
+    return out, d
+
+
+def gram(Y: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """S = Y^T Y / n on the device (matrix-core kernel)."""
+    lib = load()
+    _check_dev(Y, "Y")
+    dt = _dtype_code(Y)
+    n, p = Y.shape
+    if out is None:
+        out = torch.empty((p, p), dtype=Y.dtype, device=Y.device)
+    _check_dev(out, "out")
+    with torch.cuda.device(Y.device):
+        code = lib.concord_gram(ctypes.c_void_p(Y.data_ptr()), n, p, dt,
+                                ctypes.c_void_p(out.data_ptr()), _stream_handle(stream))
+    _raise(code, "concord_gram")
+    return out
+
+
+def schedule(p: int):
+    """Closed-form round-robin table (host): int32 array (m, p_even // 2, 2)."""
+    import numpy as np
+    lib = load()
+    pe = p + (p & 1)
+    m, h = pe - 1, pe // 2
+    buf = np.zeros((max(m, 0), h, 2), dtype=np.int32)
+    got = lib.concord_schedule(int(p), buf.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    if got < 0:
+        raise ConcordError(int(got), strerror(int(got)))
+    return buf

@@ -1,0 +1,430 @@
+// C ABI of the solver (declared in include/concord.h): argument checks,
+// workspace, launch shapes, and the sequence set-up -> persistent sweeps ->
+// dense output for one CONCORD-PCD solve.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "../../include/concord.h"
+#include "gram.hpp"
+#include "schedule.hpp"
+#include "support.hpp"
+#include "sweep.hpp"
+
+namespace concord {
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kOutWords = 8;
+constexpr long long kSpinLimit = 1ll << 22;  // polls (~1 us each) before a barrier gives up
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// Carves one stream-ordered allocation into the solve's buffers.
+struct Workspace {
+    void *base = nullptr;
+    size_t bytes = 0;
+    hipStream_t stream = nullptr;
+    ~Workspace()
+    {
+        if (base)
+            (void)hipFreeAsync(base, stream);
+    }
+};
+
+struct Carver {
+    size_t off = 0;
+    template <typename X>
+    size_t take(size_t count)
+    {
+        size_t o = off;
+        off = align_up(off + sizeof(X) * count);
+        return o;
+    }
+};
+
+struct Shape {
+    int Gr, Gc, threads, w_lds, nr_max, nc_max;
+};
+
+int cu_count()
+{
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess)
+        return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    return cus;
+}
+
+int max_shared_per_block()
+{
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess)
+        return 65536;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        return 65536;
+    return v;
+}
+
+// Launch shape for one solve of size p.  Small problems run in one
+// workgroup (a workgroup barrier per colour); larger ones over a grid of
+// Gr x Gc workgroups, one per CU, with W blocks in LDS when they fit.
+template <typename T>
+int choose_shape(int p, const concord_options *o, Shape *sh)
+{
+    const int cus = std::max(1, cu_count());
+    int Gr = o ? o->row_groups : 0, Gc = o ? o->col_slices : 0;
+    int threads = o ? o->block_threads : 0;
+    int wl = o ? o->w_in_lds : 0;
+    if (Gr < 0 || Gc < 0 || threads < 0 || (threads % 64) != 0 || threads > 1024)
+        return CONCORD_EINVAL;
+    if (Gr == 0 && Gc == 0) {
+        if (p <= 96) {
+            Gr = Gc = 1;
+        } else {
+            Gc = p < 512 ? 1 : (p < 2048 ? 4 : 8);
+            Gr = std::max(1, cus / Gc);
+        }
+    } else if (Gr == 0) {
+        Gr = std::max(1, cus / Gc);
+    } else if (Gc == 0) {
+        Gc = std::max(1, cus / Gr);
+    }
+    if (Gc > p)
+        Gc = p;
+    if (Gr > p)
+        Gr = p;
+    if (threads == 0)
+        threads = (Gr * Gc == 1) ? 256 : 512;
+    sh->Gr = Gr;
+    sh->Gc = Gc;
+    sh->threads = threads;
+    sh->nr_max = (p + Gr - 1) / Gr;
+    int ncm = 0;
+    for (int b = 0; b < Gc; ++b)
+        ncm = std::max(ncm, slice_lo(b + 1, Gc, p) - slice_lo(b, Gc, p));
+    sh->nc_max = ncm;
+    const size_t base = sizeof(T) * (4 * (size_t)sh->nr_max + 16) +
+                        sizeof(int) * (2 * (size_t)sh->nr_max + 3) + sizeof(unsigned) * 16;
+    const size_t blk = sizeof(T) * (size_t)sh->nr_max * sh->nc_max;
+    const size_t cap = (size_t)max_shared_per_block();
+    const bool fits = base + blk <= cap;
+    if (wl == 1 && !fits)
+        return CONCORD_EINVAL;
+    if (base > cap)
+        return CONCORD_ELAUNCH;
+    sh->w_lds = (wl == 1) ? 1 : (wl == 2 ? 0 : (fits ? 1 : 0));
+    return CONCORD_OK;
+}
+
+int map_hip(hipError_t e)
+{
+    if (e == hipSuccess)
+        return CONCORD_OK;
+    if (e == hipErrorOutOfMemory)
+        return CONCORD_ENOMEM;
+    if (e == hipErrorCooperativeLaunchTooLarge || e == hipErrorLaunchOutOfResources)
+        return CONCORD_ELAUNCH;
+    return CONCORD_EDEVICE;
+}
+
+#define CK_HIP(x)                            \
+    do {                                     \
+        hipError_t e_ = (x);                 \
+        if (e_ != hipSuccess)                \
+            return map_hip(e_);              \
+    } while (0)
+
+template <typename T>
+int fit_impl(concord_input kind, const void *X, int64_t n64, int64_t p64, double lambda,
+             double tol, int32_t maxit, const void *omega0, void *omega, concord_info *info,
+             hipStream_t stream, const concord_options *opts)
+{
+    const int p = (int)p64, n = (int)n64;
+    Shape sh;
+    int rc = choose_shape<T>(p, opts, &sh);
+    if (rc)
+        return rc;
+    const Circle C = Circle::make(p);
+    const int G = sh.Gr * sh.Gc;
+
+    // Events: [0] call start, [1] call end, [2]/[3] around the Gram kernel,
+    // [4]/[5] around the persistent sweep kernel (all on `stream`).
+    hipEvent_t ev[6] = {};
+    struct EvGuard {
+        hipEvent_t *e;
+        ~EvGuard()
+        {
+            for (int k = 0; k < 6; ++k)
+                if (e[k])
+                    (void)hipEventDestroy(e[k]);
+        }
+    } evg{ev};
+    for (int k = 0; k < 6; ++k)
+        CK_HIP(hipEventCreate(&ev[k]));
+    CK_HIP(hipEventRecord(ev[0], stream));
+
+    // Workspace layout.
+    Carver cv;
+    const size_t pp = (size_t)p * p;
+    const size_t oS = (kind == CONCORD_INPUT_Y) ? cv.take<T>(pp) : 0;
+    const size_t oW = cv.take<T>(pp);
+    const size_t oOmc = cv.take<T>((size_t)C.m * C.H);
+    const size_t oOmd = cv.take<T>(p);
+    const size_t oSd = cv.take<T>(p);
+    const size_t oPub = cv.take<T>(2 * (size_t)p);
+    const size_t oPubd = cv.take<T>(2 * (size_t)p);
+    const size_t oFlags = cv.take<unsigned>(G);
+    const size_t oRed = cv.take<unsigned long long>(4 * (size_t)maxit);
+    const size_t oOut = cv.take<int>(kOutWords);
+    const size_t oAcc = cv.take<double>(4);
+    Workspace ws;
+    ws.stream = stream;
+    ws.bytes = cv.off;
+    {
+        hipError_t e = hipMallocAsync(&ws.base, ws.bytes, stream);
+        if (e != hipSuccess) {
+            ws.base = nullptr;
+            return map_hip(e);
+        }
+    }
+    char *B = (char *)ws.base;
+    T *S = (kind == CONCORD_INPUT_Y) ? (T *)(B + oS) : (T *)X;
+    T *W = (T *)(B + oW);
+    T *omc = (T *)(B + oOmc), *omd = (T *)(B + oOmd), *sd = (T *)(B + oSd);
+    T *pub = (T *)(B + oPub), *pubd = (T *)(B + oPubd);
+    unsigned *flags = (unsigned *)(B + oFlags);
+    unsigned long long *red = (unsigned long long *)(B + oRed);
+    int *out = (int *)(B + oOut);
+    double *acc = (double *)(B + oAcc);
+    unsigned long long *nnz = (unsigned long long *)(acc + 2);
+
+    CK_HIP(launch_clear(flags, G, red, 4 * maxit, out, kOutWords, acc, 4, stream));
+    if (kind == CONCORD_INPUT_Y) {
+        CK_HIP(hipEventRecord(ev[2], stream));
+        CK_HIP(launch_gram<T>((const T *)X, n, p, S, stream));
+        CK_HIP(hipEventRecord(ev[3], stream));
+    }
+    CK_HIP(launch_check_copy<T>(S, p, W, omega0 == nullptr, sd, out + 4, stream));
+    if (omega0)
+        CK_HIP(launch_atb<T>((const T *)omega0, S, p, p, p, W, stream));
+    CK_HIP(launch_init_omega<T>((const T *)omega0, p, omc, omd, out + 4, stream));
+    CK_HIP(launch_init_publish<T>(W, p, pub, pubd, stream));
+
+    SweepParams<T> P;
+    memset(&P, 0, sizeof(P));
+    P.S = S;
+    P.sd = sd;
+    P.W = W;
+    P.omc = omc;
+    P.omd = omd;
+    P.pub = pub;
+    P.pubd = pubd;
+    P.flags = flags;
+    P.red = red;
+    P.out = out;
+    P.p = p;
+    P.Gr = sh.Gr;
+    P.Gc = sh.Gc;
+    P.maxit = maxit;
+    P.w_lds = sh.w_lds;
+    P.nr_max = sh.nr_max;
+    P.nc_max = sh.nc_max;
+    P.lam = (T)lambda;
+    P.tol = (T)tol;
+    P.tol_coef = (sizeof(T) == 4) ? T(16.0 * 1.1920928955078125e-07) : T(0);  // 16 eps_f32
+    P.spin_limit = kSpinLimit;
+    CK_HIP(hipEventRecord(ev[4], stream));
+    CK_HIP(launch_sweep<T>(P, sh.threads, stream));
+    CK_HIP(hipEventRecord(ev[5], stream));
+    CK_HIP(launch_finalize<T>(omc, omd, W, p, (T)lambda, (T *)omega, acc, nnz, out + 4, stream));
+    CK_HIP(hipEventRecord(ev[1], stream));
+
+    // One readback: status words, summary accumulators and the per-sweep
+    // reductions (2 * maxit words, a few KB).
+    int hout[kOutWords];
+    double hacc[2];
+    unsigned long long hnnz = 0;
+    std::vector<unsigned long long> hred(4 * (size_t)maxit);
+    CK_HIP(hipMemcpyAsync(hout, out, sizeof(hout), hipMemcpyDeviceToHost, stream));
+    CK_HIP(hipMemcpyAsync(hacc, acc, sizeof(hacc), hipMemcpyDeviceToHost, stream));
+    CK_HIP(hipMemcpyAsync(&hnnz, nnz, sizeof(hnnz), hipMemcpyDeviceToHost, stream));
+    CK_HIP(hipMemcpyAsync(hred.data(), red, sizeof(unsigned long long) * hred.size(),
+                          hipMemcpyDeviceToHost, stream));
+    CK_HIP(hipStreamSynchronize(stream));
+    float ms = 0.f, ms_gram = 0.f, ms_sweep = 0.f;
+    (void)hipEventElapsedTime(&ms, ev[0], ev[1]);
+    if (kind == CONCORD_INPUT_Y)
+        (void)hipEventElapsedTime(&ms_gram, ev[2], ev[3]);
+    (void)hipEventElapsedTime(&ms_sweep, ev[4], ev[5]);
+    const int sweeps = hout[0];
+
+    auto bits_to = [](unsigned long long u) -> double {
+        if (sizeof(T) == 8) {
+            double d;
+            memcpy(&d, &u, 8);
+            return d;
+        }
+        uint32_t w = (uint32_t)u;
+        float f;
+        memcpy(&f, &w, 4);
+        return (double)f;
+    };
+    double *trace = opts ? opts->delta_trace : nullptr;
+    if (trace)
+        for (int t = 0; t < sweeps && t < maxit; ++t)
+            trace[t] = bits_to(hred[4 * (size_t)t]);
+    unsigned long long last[2] = {0, 0};
+    int64_t moved = 0, moved_d = 0;
+    for (int t = 0; t < sweeps && t < maxit; ++t) {
+        moved += (int64_t)hred[4 * (size_t)t + 2];
+        moved_d += (int64_t)hred[4 * (size_t)t + 3];
+    }
+    if (sweeps > 0) {
+        last[0] = hred[4 * (size_t)(sweeps - 1)];
+        last[1] = hred[4 * (size_t)(sweeps - 1) + 1];
+    }
+    const double delta = bits_to(last[0]);
+    const double gmax = bits_to(last[1]);
+    const double tol_eff = std::max(tol, (double)P.tol_coef * gmax);
+
+    int status;
+    if (hout[4] & kErrNotPD)
+        status = CONCORD_ENOTPD;
+    else if (hout[4] & kErrNonFinite)
+        status = CONCORD_ENONFINITE;
+    else if (hout[2] || hout[3])
+        status = CONCORD_EDEVICE;
+    else
+        status = hout[1] ? CONCORD_OK : CONCORD_NOT_CONVERGED;
+    if (info) {
+        info->sweeps = sweeps;
+        info->status = status;
+        info->delta = delta;
+        info->tol_eff = tol_eff;
+        info->nnz_upper = (int64_t)hnnz;
+        info->objective = hacc[0];
+        info->elapsed_ms = ms;
+        info->gram_ms = ms_gram;
+        info->sweep_ms = ms_sweep;
+        info->moved_pairs = moved;
+        info->moved_diag = moved_d;
+        info->row_groups = sh.Gr;
+        info->col_slices = sh.Gc;
+        info->w_in_lds = sh.w_lds;
+        info->block_threads = sh.threads;
+    }
+    return status;
+}
+
+int validate(concord_input kind, const void *X, int64_t n, int64_t p, double lambda, double tol,
+             int32_t maxit, concord_dtype dt, void *omega)
+{
+    if (!X || !omega)
+        return CONCORD_EINVAL;
+    if (kind != CONCORD_INPUT_S && kind != CONCORD_INPUT_Y)
+        return CONCORD_EINVAL;
+    if (dt != CONCORD_F32 && dt != CONCORD_F64)
+        return CONCORD_EINVAL;
+    if (p < 1 || p > 46340)  // p * p must index as int64 and rows as int32
+        return CONCORD_EINVAL;
+    if (kind == CONCORD_INPUT_Y && (n < 1 || n > INT32_MAX))
+        return CONCORD_EINVAL;
+    if (!(lambda >= 0.0) || !isfinite(lambda))
+        return CONCORD_EINVAL;
+    if (!(tol > 0.0) || !isfinite(tol))
+        return CONCORD_EINVAL;
+    if (maxit < 1)
+        return CONCORD_EINVAL;
+    return CONCORD_OK;
+}
+
+}  // namespace
+}  // namespace concord
+
+using namespace concord;
+
+extern "C" int concord_fit_ex(concord_input kind, const void *X, int64_t n, int64_t p,
+                              double lambda, double tol, int32_t maxit, concord_dtype dt,
+                              const void *omega0, void *omega, concord_info *info, void *stream,
+                              const concord_options *opts)
+{
+    int rc = validate(kind, X, n, p, lambda, tol, maxit, dt, omega);
+    if (rc) {
+        if (info) {
+            memset(info, 0, sizeof(*info));
+            info->status = rc;
+        }
+        return rc;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    if (dt == CONCORD_F64)
+        return fit_impl<double>(kind, X, n, p, lambda, tol, maxit, omega0, omega, info, st, opts);
+    return fit_impl<float>(kind, X, n, p, lambda, tol, maxit, omega0, omega, info, st, opts);
+}
+
+extern "C" int concord_fit(concord_input kind, const void *X, int64_t n, int64_t p, double lambda,
+                           double tol, int32_t maxit, concord_dtype dt, const void *omega0,
+                           void *omega, concord_info *info, void *stream)
+{
+    return concord_fit_ex(kind, X, n, p, lambda, tol, maxit, dt, omega0, omega, info, stream,
+                          nullptr);
+}
+
+extern "C" int concord_gram(const void *Y, int64_t n, int64_t p, concord_dtype dt, void *S,
+                            void *stream)
+{
+    if (!Y || !S || n < 1 || n > INT32_MAX || p < 1 || p > 46340)
+        return CONCORD_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e;
+    if (dt == CONCORD_F64)
+        e = launch_gram<double>((const double *)Y, (int)n, (int)p, (double *)S, st);
+    else if (dt == CONCORD_F32)
+        e = launch_gram<float>((const float *)Y, (int)n, (int)p, (float *)S, st);
+    else
+        return CONCORD_EINVAL;
+    if (e != hipSuccess)
+        return map_hip(e);
+    return map_hip(hipStreamSynchronize(st));
+}
+
+extern "C" int64_t concord_schedule(int64_t p, int32_t *pairs)
+{
+    if (p < 1 || p > 46340 || !pairs)
+        return CONCORD_EINVAL;
+    const Circle C = Circle::make((int)p);
+    for (int r = 0; r < C.m; ++r)
+        for (int q = 0; q < C.H; ++q) {
+            int a, b;
+            C.pair(r, q, &a, &b);
+            pairs[((size_t)r * C.H + q) * 2 + 0] = a;
+            pairs[((size_t)r * C.H + q) * 2 + 1] = b;
+        }
+    return C.m;
+}
+
+extern "C" const char *concord_strerror(int code)
+{
+    switch (code) {
+    case CONCORD_OK: return "converged";
+    case CONCORD_NOT_CONVERGED: return "sweep limit reached before the tolerance (last iterate returned)";
+    case CONCORD_EINVAL: return "invalid argument";
+    case CONCORD_ENONFINITE: return "non-finite value in the input or the iteration";
+    case CONCORD_ENOTPD: return "a diagonal entry of S is not positive";
+    case CONCORD_ENOMEM: return "device workspace allocation failed";
+    case CONCORD_EDEVICE: return "HIP runtime error or a device wait exceeded its bound";
+    case CONCORD_ELAUNCH: return "launch shape cannot be made co-resident on this device";
+    default: return "unknown status code";
+    }
+}
+
+extern "C" const char *concord_version(void) { return "concord-mi355x 0.1.0 (gfx950)"; }

@@ -1,0 +1,25 @@
+// Set-up and output kernels around the persistent sweep.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace concord {
+
+// Bits of the device error word.
+constexpr int kErrNonFinite = 1;  // NaN/Inf in an input or in the result
+constexpr int kErrNotPD = 2;      // some S_ii <= 0
+
+template <typename T>
+hipError_t launch_check_copy(const T *S, int p, T *W, bool copy_w, T *sd, int *err,
+                             hipStream_t st);
+template <typename T>
+hipError_t launch_init_omega(const T *omega0, int p, T *omc, T *omd, int *err, hipStream_t st);
+hipError_t launch_clear(unsigned *flags, int nflags, unsigned long long *red, int nred, int *out,
+                        int nout, double *acc, int nacc, hipStream_t st);
+template <typename T>
+hipError_t launch_init_publish(const T *W, int p, T *pub, T *pubd, hipStream_t st);
+template <typename T>
+hipError_t launch_finalize(const T *omc, const T *omd, const T *W, int p, T lam, T *omega,
+                           double *acc, unsigned long long *nnz, int *err, hipStream_t st);
+
+}  // namespace concord

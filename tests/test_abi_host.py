@@ -1,0 +1,91 @@
+"""Host-side checks of the C ABI (no GPU needed).
+
+* The library loads and exports every function include/concord.h declares.
+* concord_schedule (the closed form the kernels use) equals the oracle's
+  literal round-robin rotation bit for bit, slot order included.
+* Invalid arguments are rejected before any device work.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "concord.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(concord_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2106_09382_amd import _lib
+    return _lib.load()
+
+
+def test_header_declares_the_entry_points():
+    names = _declared_functions()
+    for want in ("concord_fit", "concord_fit_ex", "concord_gram", "concord_schedule",
+                 "concord_strerror", "concord_version"):
+        assert want in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in _declared_functions():
+        assert hasattr(lib, name), name
+
+
+@pytest.mark.parametrize("p", list(range(1, 130)) + [255, 256, 1000, 1001, 2000, 2001])
+def test_closed_form_schedule_matches_literal_rotation(p):
+    from paper_2106_09382_amd import _lib
+    assert np.array_equal(_lib.schedule(p), oracle.round_robin(p))
+
+
+def test_schedule_rejects_bad_p(lib):
+    buf = (ctypes.c_int32 * 4)()
+    assert lib.concord_schedule(0, buf) == -1
+    assert lib.concord_schedule(-3, buf) == -1
+    assert lib.concord_schedule(4, None) == -1
+
+
+def test_strerror_covers_codes(lib):
+    for c in (0, 1, -1, -2, -3, -4, -5, -6):
+        s = lib.concord_strerror(c).decode()
+        assert s and s != "unknown status code"
+    assert lib.concord_strerror(99).decode() == "unknown status code"
+    assert b"gfx950" in lib.concord_version()
+
+
+def _fit(lib, **kw):
+    from paper_2106_09382_amd import _lib
+    a = dict(kind=0, X=ctypes.c_void_p(0x1000), n=0, p=8, lam=0.1, tol=1e-6, maxit=10, dt=1,
+             omega0=None, omega=ctypes.c_void_p(0x2000))
+    a.update(kw)
+    info = _lib.ConcordInfo()
+    rc = lib.concord_fit(a["kind"], a["X"], a["n"], a["p"], a["lam"], a["tol"], a["maxit"],
+                         a["dt"], a["omega0"], a["omega"], ctypes.byref(info), None)
+    return rc, info
+
+
+@pytest.mark.parametrize("kw", [
+    dict(X=None), dict(omega=None), dict(p=0), dict(p=-5), dict(p=50000),
+    dict(lam=-0.1), dict(lam=float("nan")), dict(lam=float("inf")),
+    dict(tol=0.0), dict(tol=-1.0), dict(tol=float("nan")), dict(maxit=0),
+    dict(dt=7), dict(kind=5), dict(kind=1, n=0),
+])
+def test_invalid_arguments_return_einval(lib, kw):
+    rc, info = _fit(lib, **kw)
+    assert rc == -1 and info.status == -1
+
+
+def test_gram_rejects_bad_sizes(lib):
+    assert lib.concord_gram(None, 10, 10, 1, ctypes.c_void_p(0x10), None) == -1
+    assert lib.concord_gram(ctypes.c_void_p(0x10), 0, 10, 1, ctypes.c_void_p(0x10), None) == -1
+    assert lib.concord_gram(ctypes.c_void_p(0x10), 10, 10, 3, ctypes.c_void_p(0x10), None) == -1
