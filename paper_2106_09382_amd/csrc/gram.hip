@@ -9,9 +9,10 @@
 // one for the tile's rows and one for its columns (the same panel on the
 // diagonal).
 //
-// MFMA 16x16x4 (f64 and f32) operand layout, lane l of the wave:
+// MFMA 16x16x4 operand layout, lane l of the wave (checked on gfx950):
 //   A (16 x 4):  A[l % 16][l / 16]      B (4 x 16):  B[l / 16][l % 16]
-//   D (16 x 16): register v holds D[4 (l / 16) + v][l % 16]
+//   D (16 x 16): result element v of lane l is D[row][l % 16] with
+//                row = 4 (l / 16) + v  for f32,   row = l / 16 + 4 v  for f64.
 // Here A = Y^T restricted to 16 tile rows and 4 k values, B = Y likewise.
 #include <hip/hip_runtime.h>
 
@@ -34,6 +35,7 @@ struct Mfma<double> {
     {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
     }
+    __device__ static int row(int lane, int v) { return (lane >> 4) + 4 * v; }
 };
 
 template <>
@@ -43,6 +45,7 @@ struct Mfma<float> {
     {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
     }
+    __device__ static int row(int lane, int v) { return 4 * (lane >> 4) + v; }
 };
 
 }  // namespace
@@ -118,7 +121,7 @@ __global__ void __launch_bounds__(256) atb_mfma_kernel(const T *__restrict__ A,
     for (int x = 0; x < 2; ++x)
         for (int y = 0; y < 2; ++y)
             for (int v = 0; v < 4; ++v) {
-                const int i = I0 + qi + 16 * x + 4 * (lane >> 4) + v;
+                const int i = I0 + qi + 16 * x + Mfma<T>::row(lane, v);
                 const int j = J0 + qj + 16 * y + (lane & 15);
                 if (i < M && j < N) {
                     const T val = acc[x][y][v] * scale;

@@ -8,27 +8,31 @@ namespace concord {
 
 // Workspace of one solve (all device pointers).  The layout in HBM:
 //   S     p x p row-major (read-only during the sweeps)
-//   W     p x p row-major, the maintained product W = Omega S; workgroup (a, b)
-//         owns rows i = a (mod Gr) restricted to column slice b
-//   omc   colour-major off-diagonals: omc[r * H + q] = omega of slot q of colour r
-//   omd   diagonal, p
+//   W     p x p row-major, the maintained product W = Omega S; workgroup
+//         g = a * Gc + b owns rows i = a (mod Gr) restricted to column slice b
+//   omp   per-workgroup copies of omega: omp[(g * m + r) * nr_max + k] is
+//         omega_{i, partner_r(i)} for the workgroup's k-th row i = a + k Gr
+//   omdp  per-workgroup diagonals: omdp[g * nr_max + k] = omega_ii
 //   sd    diag(S), p
-//   pub   2 x p: pub[(s & 1) * p + i] = W_{i, partner_r(i)} for global step s
-//   pubd  2 x p: pubd[(t & 1) * p + i] = W_ii just before the last colour of sweep t
-//   flags one arrival word per workgroup (barrier epochs)
+//   pc    published numerator entries, two sweep-parity buffers:
+//         pc[(buf * m + r) * p + i] = W_{i, partner_r(i)} as colour r reads it
+//   pd    pd[buf * p + i] = W_ii as the last colour reads it
+//   flags one sweep-barrier word per workgroup (epochs)
 //   red   per sweep t, 4 words: [4t] max |change| (bits), [4t+1] max omega_ii (bits),
 //         [4t+2] pairs that changed, [4t+3] diagonals that changed
-//   out   [0] sweeps, [1] converged, [2] device wait failed, [3] abort flag,
+//   out   [0] sweeps, [1] converged, [2] a device wait failed, [3] abort flag,
 //         [4] input error bits from the set-up kernels
+// Entries of pc (colours >= 1) and pd are reset to a signalling-NaN sentinel
+// one sweep before they are written; a reader polls until the sentinel is gone.
 template <typename T>
 struct SweepParams {
     const T *S;
     const T *sd;
     T *W;
-    T *omc;
-    T *omd;
-    T *pub;
-    T *pubd;
+    T *omp;
+    T *omdp;
+    T *pc;
+    T *pd;
     unsigned *flags;
     unsigned long long *red;
     int *out;
@@ -38,6 +42,8 @@ struct SweepParams {
     int w_lds;         // W block resident in LDS
     int nr_max;        // max rows per workgroup = ceil(p / Gr)
     int nc_max;        // max columns per workgroup
+    int depth;         // pending row updates held before a row is flushed (>= 2)
+    int rpt;           // rows per thread (1, 2 or 4)
     T lam;
     T tol;
     T tol_coef;        // tol_eff = max(tol, tol_coef * max_i omega_ii)
@@ -47,8 +53,22 @@ struct SweepParams {
 // Column slice b of Gc over p columns: [slice_lo(b), slice_lo(b + 1)).
 __host__ __device__ inline int slice_lo(int b, int Gc, int p) { return (int)(((long long)b * p) / Gc); }
 
+// Sentinel bit patterns (signalling NaNs: arithmetic never produces them).
 template <typename T>
-size_t sweep_lds_bytes(const SweepParams<T> &P, int threads);
+struct Sentinel;
+template <>
+struct Sentinel<double> {
+    using U = unsigned long long;
+    static constexpr U bits = 0x7FF4DEAD0000BEEFull;
+};
+template <>
+struct Sentinel<float> {
+    using U = unsigned int;
+    static constexpr U bits = 0x7FA0BEEFu;
+};
+
+template <typename T>
+size_t sweep_lds_bytes(const SweepParams<T> &P);
 
 template <typename T>
 hipError_t launch_sweep(const SweepParams<T> &P, int threads, hipStream_t stream);
