@@ -98,7 +98,17 @@ def main() -> int:
     ap.add_argument("--threads", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--dump-y", metavar="PATH",
+                    help="write the workload's Y (raw float64, n x p) to PATH and exit; "
+                         "input for the native driver concord_bench")
     args = ap.parse_args()
+
+    if args.dump_y:
+        from paper_2106_09382_amd import datagen
+        pr = datagen.problem(3, graph=args.graph, p=args.p, n=args.n)
+        pr["y"].astype("<f8").tofile(args.dump_y)
+        log(f"bench: wrote Y ({args.n} x {args.p}, seed {pr['seed']}) to {args.dump_y}")
+        return 0
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

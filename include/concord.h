@@ -67,15 +67,26 @@ typedef struct {
     int32_t col_slices; /*   ... and the columns */
     int32_t w_in_lds;   /*   1 if W blocks were held in LDS */
     int32_t block_threads;
+    int32_t pending_depth; /* row updates held back before a row of W is rewritten */
+    int32_t reserved;
 } concord_info;
 
 /* Launch/tuning options; zero-initialise for defaults. */
 typedef struct {
     int32_t row_groups;     /* workgroups sharing out the rows of W (0 = auto) */
     int32_t col_slices;     /* workgroups sharing out the columns of W (0 = auto) */
-    int32_t block_threads;  /* threads per workgroup, multiple of 64 (0 = auto) */
+    int32_t block_threads;  /* threads per workgroup, multiple of 64, <= 512 (0 = auto) */
     int32_t w_in_lds;       /* -1/0 = auto, 1 = force W blocks in LDS, 2 = force W in HBM */
+    int32_t pending_depth;  /* 0 = auto, else 2..8: updates a row holds before it is rewritten */
     double *delta_trace;    /* optional host array of maxit entries: delta of every sweep */
+    /* Optional device array of workgroups x timestamp_steps x 3 words: for
+     * each of the first timestamp_steps colour steps, thread 0 of every
+     * workgroup stores the 100 MHz device clock at the step's start, when its
+     * rows are done, and when its row rewrites are done.  Query the launch
+     * shape first (a call with the same options returns it in concord_info). */
+    uint64_t *device_timestamps;
+    int32_t timestamp_steps;
+    int32_t reserved;
 } concord_options;
 
 /*

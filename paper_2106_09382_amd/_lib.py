@@ -39,6 +39,8 @@ class ConcordInfo(ctypes.Structure):
         ("col_slices", ctypes.c_int32),
         ("w_in_lds", ctypes.c_int32),
         ("block_threads", ctypes.c_int32),
+        ("pending_depth", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:
@@ -51,7 +53,11 @@ class ConcordOptions(ctypes.Structure):
         ("col_slices", ctypes.c_int32),
         ("block_threads", ctypes.c_int32),
         ("w_in_lds", ctypes.c_int32),
+        ("pending_depth", ctypes.c_int32),
         ("delta_trace", ctypes.POINTER(ctypes.c_double)),
+        ("device_timestamps", ctypes.c_void_p),
+        ("timestamp_steps", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -131,7 +137,8 @@ def _raise(code: int, what: str):
 def fit(X: torch.Tensor, lam: float, tol: float = 1e-6, maxit: int = 500, *, kind: str = "S",
         omega0: torch.Tensor | None = None, out: torch.Tensor | None = None, stream=None,
         row_groups: int = 0, col_slices: int = 0, block_threads: int = 0, w_in_lds: int = 0,
-        trace: bool = False, check: bool = True):
+        pending_depth: int = 0, trace: bool = False, check: bool = True,
+        timestamps: torch.Tensor | None = None):
     """One CONCORD-PCD solve.  X is S (p x p) or, with kind='Y', Y (n x p).
 
     Returns (omega, info dict); info['delta_trace'] holds every sweep's delta
@@ -163,7 +170,13 @@ def fit(X: torch.Tensor, lam: float, tol: float = 1e-6, maxit: int = 500, *, kin
             raise ValueError("omega0 must be p x p with X's dtype")
         o0 = ctypes.c_void_p(omega0.data_ptr())
     info = ConcordInfo()
-    opts = ConcordOptions(row_groups, col_slices, block_threads, w_in_lds, None)
+    opts = ConcordOptions(row_groups, col_slices, block_threads, w_in_lds, pending_depth, None,
+                          None, 0, 0)
+    if timestamps is not None:
+        # int64 device tensor of shape (workgroups, steps, 3)
+        _check_dev(timestamps, "timestamps")
+        opts.device_timestamps = timestamps.data_ptr()
+        opts.timestamp_steps = int(timestamps.shape[1])
     tr = None
     if trace:
         tr = (ctypes.c_double * int(maxit))()

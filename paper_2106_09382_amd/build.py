@@ -39,8 +39,12 @@ def _compile(src: str) -> str:
     return obj
 
 
+BENCH = os.path.join(HERE, "concord_bench")
+
+
 def build(jobs: int = 8) -> str:
-    """Compile all HIP sources and link libconcord.so; returns its path."""
+    """Compile all HIP sources, link libconcord.so and the native benchmark
+    driver concord_bench; returns the library path."""
     os.makedirs(OBJ, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
@@ -51,6 +55,13 @@ def build(jobs: int = 8) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
     os.replace(tmp, LIB)
+    tmpb = BENCH + ".tmp"
+    cmd = [_hipcc(), "-O2", "-std=c++17", os.path.join(CSRC, "bench_main.cpp"), "-o", tmpb,
+           "-L", HERE, "-lconcord", "-Wl,-rpath,$ORIGIN"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"concord_bench build failed:\n{r.stderr}")
+    os.replace(tmpb, BENCH)
     return LIB
 
 

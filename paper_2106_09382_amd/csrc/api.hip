@@ -51,7 +51,7 @@ struct Carver {
 };
 
 struct Shape {
-    int Gr, Gc, threads, w_lds, nr_max, nc_max;
+    int Gr, Gc, threads, w_lds, nr_max, nc_max, depth, rpt;
 };
 
 int cu_count()
@@ -75,8 +75,9 @@ int max_shared_per_block()
 }
 
 // Launch shape for one solve of size p.  Small problems run in one
-// workgroup (a workgroup barrier per colour); larger ones over a grid of
-// Gr x Gc workgroups, one per CU, with W blocks in LDS when they fit.
+// workgroup; larger ones over a grid of Gr x Gc workgroups, one per CU, with
+// W blocks in LDS when they fit.  Rows of a workgroup are dealt to threads,
+// at most four per thread.
 template <typename T>
 int choose_shape(int p, const concord_options *o, Shape *sh)
 {
@@ -84,13 +85,15 @@ int choose_shape(int p, const concord_options *o, Shape *sh)
     int Gr = o ? o->row_groups : 0, Gc = o ? o->col_slices : 0;
     int threads = o ? o->block_threads : 0;
     int wl = o ? o->w_in_lds : 0;
-    if (Gr < 0 || Gc < 0 || threads < 0 || (threads % 64) != 0 || threads > 1024)
+    int depth = o ? o->pending_depth : 0;
+    if (Gr < 0 || Gc < 0 || threads < 0 || (threads % 64) != 0 || threads > 512 || depth < 0 ||
+        depth == 1 || depth > 8)
         return CONCORD_EINVAL;
     if (Gr == 0 && Gc == 0) {
         if (p <= 96) {
             Gr = Gc = 1;
         } else {
-            Gc = p < 512 ? 1 : (p < 2048 ? 4 : 8);
+            Gc = p < 512 ? 1 : (p < 2048 ? 2 : 8);
             Gr = std::max(1, cus / Gc);
         }
     } else if (Gr == 0) {
@@ -102,26 +105,39 @@ int choose_shape(int p, const concord_options *o, Shape *sh)
         Gc = p;
     if (Gr > p)
         Gr = p;
-    if (threads == 0)
-        threads = (Gr * Gc == 1) ? 256 : 512;
     sh->Gr = Gr;
     sh->Gc = Gc;
-    sh->threads = threads;
     sh->nr_max = (p + Gr - 1) / Gr;
+    if (threads == 0)
+        threads = (Gr * Gc == 1) ? 256 : 512;
+    sh->threads = threads;
+    sh->rpt = (sh->nr_max + threads - 1) / threads;
+    if (sh->rpt > 2)
+        return CONCORD_ELAUNCH;
+    if (sh->rpt < 1)
+        sh->rpt = 1;
     int ncm = 0;
     for (int b = 0; b < Gc; ++b)
         ncm = std::max(ncm, slice_lo(b + 1, Gc, p) - slice_lo(b, Gc, p));
     sh->nc_max = ncm;
-    const size_t base = sizeof(T) * (4 * (size_t)sh->nr_max + 16) +
-                        sizeof(int) * (2 * (size_t)sh->nr_max + 3) + sizeof(unsigned) * 16;
-    const size_t blk = sizeof(T) * (size_t)sh->nr_max * sh->nc_max;
     const size_t cap = (size_t)max_shared_per_block();
-    const bool fits = base + blk <= cap;
+    auto lds_need = [&](int d, bool w) {
+        size_t b = sizeof(T) * ((size_t)sh->nr_max * d + 16) +
+                   sizeof(int) * ((size_t)sh->nr_max * d + 2 * (size_t)sh->nr_max + 4) +
+                   sizeof(unsigned) * 16;
+        if (w)
+            b += sizeof(T) * (size_t)sh->nr_max * sh->nc_max;
+        return b;
+    };
+    // W in LDS: updates are cheap, apply them at once (depth 2).  W in HBM:
+    // hold up to 8 pending updates per row.
+    const bool fits = lds_need(depth ? depth : 2, true) <= cap;
     if (wl == 1 && !fits)
         return CONCORD_EINVAL;
-    if (base > cap)
-        return CONCORD_ELAUNCH;
     sh->w_lds = (wl == 1) ? 1 : (wl == 2 ? 0 : (fits ? 1 : 0));
+    sh->depth = depth ? depth : (sh->w_lds ? 2 : 8);
+    if (lds_need(sh->depth, sh->w_lds) > cap)
+        return CONCORD_ELAUNCH;
     return CONCORD_OK;
 }
 
@@ -177,11 +193,12 @@ int fit_impl(concord_input kind, const void *X, int64_t n64, int64_t p64, double
     const size_t pp = (size_t)p * p;
     const size_t oS = (kind == CONCORD_INPUT_Y) ? cv.take<T>(pp) : 0;
     const size_t oW = cv.take<T>(pp);
-    const size_t oOmc = cv.take<T>((size_t)C.m * C.H);
-    const size_t oOmd = cv.take<T>(p);
+    const size_t oOmp = cv.take<T>((size_t)G * C.m * sh.nr_max);
+    const size_t oOmdp = cv.take<T>((size_t)G * sh.nr_max);
     const size_t oSd = cv.take<T>(p);
-    const size_t oPub = cv.take<T>(2 * (size_t)p);
-    const size_t oPubd = cv.take<T>(2 * (size_t)p);
+    const size_t PS = (size_t)sh.Gr * sh.nr_max;  // published slots per colour
+    const size_t oPc = cv.take<T>(2 * (size_t)C.m * PS);
+    const size_t oPd = cv.take<T>(2 * PS);
     const size_t oFlags = cv.take<unsigned>(G);
     const size_t oRed = cv.take<unsigned long long>(4 * (size_t)maxit);
     const size_t oOut = cv.take<int>(kOutWords);
@@ -199,8 +216,8 @@ int fit_impl(concord_input kind, const void *X, int64_t n64, int64_t p64, double
     char *B = (char *)ws.base;
     T *S = (kind == CONCORD_INPUT_Y) ? (T *)(B + oS) : (T *)X;
     T *W = (T *)(B + oW);
-    T *omc = (T *)(B + oOmc), *omd = (T *)(B + oOmd), *sd = (T *)(B + oSd);
-    T *pub = (T *)(B + oPub), *pubd = (T *)(B + oPubd);
+    T *omp = (T *)(B + oOmp), *omdp = (T *)(B + oOmdp), *sd = (T *)(B + oSd);
+    T *pc = (T *)(B + oPc), *pd = (T *)(B + oPd);
     unsigned *flags = (unsigned *)(B + oFlags);
     unsigned long long *red = (unsigned long long *)(B + oRed);
     int *out = (int *)(B + oOut);
@@ -216,18 +233,19 @@ int fit_impl(concord_input kind, const void *X, int64_t n64, int64_t p64, double
     CK_HIP(launch_check_copy<T>(S, p, W, omega0 == nullptr, sd, out + 4, stream));
     if (omega0)
         CK_HIP(launch_atb<T>((const T *)omega0, S, p, p, p, W, stream));
-    CK_HIP(launch_init_omega<T>((const T *)omega0, p, omc, omd, out + 4, stream));
-    CK_HIP(launch_init_publish<T>(W, p, pub, pubd, stream));
+    CK_HIP(launch_init_omega<T>((const T *)omega0, p, sh.Gr, sh.Gc, sh.nr_max, omp, omdp, out + 4,
+                                stream));
+    CK_HIP(launch_init_publish<T>(W, p, sh.Gr, sh.nr_max, pc, pd, stream));
 
     SweepParams<T> P;
     memset(&P, 0, sizeof(P));
     P.S = S;
     P.sd = sd;
     P.W = W;
-    P.omc = omc;
-    P.omd = omd;
-    P.pub = pub;
-    P.pubd = pubd;
+    P.omp = omp;
+    P.omdp = omdp;
+    P.pc = pc;
+    P.pd = pd;
     P.flags = flags;
     P.red = red;
     P.out = out;
@@ -238,14 +256,19 @@ int fit_impl(concord_input kind, const void *X, int64_t n64, int64_t p64, double
     P.w_lds = sh.w_lds;
     P.nr_max = sh.nr_max;
     P.nc_max = sh.nc_max;
+    P.depth = sh.depth;
+    P.rpt = sh.rpt;
     P.lam = (T)lambda;
     P.tol = (T)tol;
     P.tol_coef = (sizeof(T) == 4) ? T(16.0 * 1.1920928955078125e-07) : T(0);  // 16 eps_f32
     P.spin_limit = kSpinLimit;
+    P.tstamp = opts ? reinterpret_cast<unsigned long long *>(opts->device_timestamps) : nullptr;
+    P.tstamp_steps = (opts && opts->device_timestamps) ? opts->timestamp_steps : 0;
     CK_HIP(hipEventRecord(ev[4], stream));
     CK_HIP(launch_sweep<T>(P, sh.threads, stream));
     CK_HIP(hipEventRecord(ev[5], stream));
-    CK_HIP(launch_finalize<T>(omc, omd, W, p, (T)lambda, (T *)omega, acc, nnz, out + 4, stream));
+    CK_HIP(launch_finalize<T>(omp, omdp, sh.Gr, sh.Gc, sh.nr_max, W, p, (T)lambda, (T *)omega, acc,
+                              nnz, out + 4, stream));
     CK_HIP(hipEventRecord(ev[1], stream));
 
     // One readback: status words, summary accumulators and the per-sweep
@@ -321,6 +344,7 @@ int fit_impl(concord_input kind, const void *X, int64_t n64, int64_t p64, double
         info->col_slices = sh.Gc;
         info->w_in_lds = sh.w_lds;
         info->block_threads = sh.threads;
+        info->pending_depth = sh.depth;
     }
     return status;
 }

@@ -5,6 +5,7 @@
 #include "device_common.hpp"
 #include "schedule.hpp"
 #include "support.hpp"
+#include "sweep.hpp"
 
 namespace concord {
 
@@ -54,34 +55,47 @@ __global__ void check_copy_kernel(const T *__restrict__ S, int p, T *__restrict_
         atomicOr(err, bad);
 }
 
-// Starting Omega in the sweep's layout: colour-major off-diagonals and the
-// diagonal.  omega0 == nullptr means the identity.
+// Starting Omega in the sweep's layout: every workgroup's own copy of
+// omega_{i, partner_r(i)} for its rows and all colours, and of omega_ii.
+// omega0 == nullptr means the identity.
 template <typename T>
-__global__ void init_omega_kernel(const T *__restrict__ omega0, int p, T *__restrict__ omc,
-                                  T *__restrict__ omd, int *__restrict__ err)
+__global__ void init_omega_kernel(const T *__restrict__ omega0, int p, int Gr, int Gc, int NR,
+                                  T *__restrict__ omp, T *__restrict__ omdp, int *__restrict__ err)
 {
     const Circle C = Circle::make(p);
-    const long long slots = (long long)C.m * C.H;
+    const int G = Gr * Gc;
+    const long long offd = (long long)G * C.m * NR;
+    const long long total = offd + (long long)G * NR;
     int bad = 0;
-    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < slots + p;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
          e += (long long)gridDim.x * blockDim.x) {
-        if (e < slots) {
-            const int r = (int)(e / C.H), q = (int)(e - (long long)r * C.H);
-            int u, v;
-            C.pair(r, q, &u, &v);
+        if (e < offd) {
+            const long long per = (long long)C.m * NR;
+            const int g = (int)(e / per);
+            const long long rem = e - (long long)g * per;
+            const int r = (int)(rem / NR), k = (int)(rem - (long long)r * NR);
+            const int i = g / Gc + k * Gr;
             T w = T(0);
-            if (omega0 && u < p && v < p) {
-                w = omega0[(size_t)u * p + v];
+            if (omega0 && i < p) {
+                const int j = C.partner(r, i);
+                if (j >= 0) {
+                    w = omega0[(size_t)i * p + j];
+                    if (!finite_v(w))
+                        bad |= kErrNonFinite;
+                }
+            }
+            omp[e] = w;
+        } else {
+            const long long e2 = e - offd;
+            const int g = (int)(e2 / NR), k = (int)(e2 - (long long)g * NR);
+            const int i = g / Gc + k * Gr;
+            T w = T(1);
+            if (omega0 && i < p) {
+                w = omega0[(size_t)i * p + i];
                 if (!finite_v(w))
                     bad |= kErrNonFinite;
             }
-            omc[e] = w;
-        } else {
-            const int i = (int)(e - slots);
-            T w = omega0 ? omega0[(size_t)i * p + i] : T(1);
-            if (!finite_v(w))
-                bad |= kErrNonFinite;
-            omd[i] = w;
+            omdp[e2] = w;
         }
     }
     if (bad)
@@ -109,30 +123,48 @@ __global__ void clear_kernel(unsigned *__restrict__ flags, int nflags,
     }
 }
 
-// First published numerator entries: pub[i] = W_{i, partner_0(i)} for the
-// first colour step and pubd[i] = W_ii (read before the last colour).
+// First published numerator entries: pc[0][colour 0][slot(i)] = W_{i, partner_0(i)};
+// every other slot of pc and pd holds the sentinel, except pd[0] when the
+// first colour is also the last (m = 1), which reads W_ii directly.  Slots
+// are group-major: row i at (i mod Gr) * NR + i / Gr, PS = Gr * NR per colour.
 template <typename T>
-__global__ void init_publish_kernel(const T *__restrict__ W, int p, T *__restrict__ pub,
-                                    T *__restrict__ pubd)
+__global__ void init_publish_kernel(const T *__restrict__ W, int p, int Gr, int NR,
+                                    T *__restrict__ pc, T *__restrict__ pd)
 {
+    using U = typename Sentinel<T>::U;
     const Circle C = Circle::make(p);
-    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < p; e += gridDim.x * blockDim.x) {
-        const int j = C.partner(0, e);
-        pub[e] = (j >= 0) ? W[(size_t)e * p + j] : T(0);
-        pub[p + e] = T(0);
-        pubd[e] = W[(size_t)e * p + e];
-        pubd[p + e] = T(0);
+    const long long PS = (long long)Gr * NR;
+    const long long npc = 2ll * C.m * PS;
+    U *pcu = reinterpret_cast<U *>(pc);
+    U *pdu = reinterpret_cast<U *>(pd);
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < npc + 2 * PS;
+         e += (long long)gridDim.x * blockDim.x) {
+        if (e < PS) {
+            const int i = (int)(e % NR) * Gr + (int)(e / NR);
+            const int j = (i < p) ? C.partner(0, i) : -1;
+            pc[e] = (j >= 0) ? W[(size_t)i * p + j] : T(0);
+        } else if (e < npc) {
+            pcu[e] = Sentinel<T>::bits;
+        } else {
+            const long long d = e - npc;
+            const int i = (int)(d % NR) * Gr + (int)(d / NR);
+            if (d < PS && C.m == 1 && i < p)
+                pd[d] = W[(size_t)i * p + i];
+            else
+                pdu[d] = Sentinel<T>::bits;
+        }
     }
 }
 
-// Dense symmetric Omega from the sweep layout, plus the summary: nonzeros
-// above the diagonal and F(Omega) = -sum log omega_ii + 1/2 sum_ij W_ij omega_ij
+// Dense symmetric Omega from the sweep layout (the copies held by the
+// workgroups of column slice 0), plus the summary: nonzeros above the
+// diagonal and F(Omega) = -sum log omega_ii + 1/2 sum_ij W_ij omega_ij
 // + lam sum_{i<j} |omega_ij| (tr(Omega S Omega) = sum_ij (Omega S)_ij omega_ij).
 template <typename T>
-__global__ void finalize_kernel(const T *__restrict__ omc, const T *__restrict__ omd,
-                                const T *__restrict__ W, int p, T lam, T *__restrict__ omega,
-                                double *__restrict__ acc, unsigned long long *__restrict__ nnz,
-                                int *__restrict__ err)
+__global__ void finalize_kernel(const T *__restrict__ omp, const T *__restrict__ omdp, int Gr,
+                                int Gc, int NR, const T *__restrict__ W, int p, T lam,
+                                T *__restrict__ omega, double *__restrict__ acc,
+                                unsigned long long *__restrict__ nnz, int *__restrict__ err)
 {
     __shared__ double sred[kThreads / 64];
     __shared__ unsigned long long sn[kThreads / 64];
@@ -144,13 +176,15 @@ __global__ void finalize_kernel(const T *__restrict__ omc, const T *__restrict__
     for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
          e += (long long)gridDim.x * blockDim.x) {
         const int i = (int)(e / p), j = (int)(e - (long long)i * p);
+        const int lo = i < j ? i : j;
+        const int g = (lo % Gr) * Gc, k = lo / Gr;
         T w;
         if (i == j) {
-            w = omd[i];
+            w = omdp[(size_t)g * NR + k];
             part += -log((double)w);
         } else {
             const int r = C.colour(i, j);
-            w = omc[(size_t)r * C.H + C.slot(r, i)];
+            w = omp[((size_t)g * C.m + r) * NR + k];
             if (i < j) {
                 part += (double)lam * fabs((double)w);
                 cnt += (w != T(0));
@@ -195,11 +229,13 @@ hipError_t launch_check_copy(const T *S, int p, T *W, bool copy_w, T *sd, int *e
 }
 
 template <typename T>
-hipError_t launch_init_omega(const T *omega0, int p, T *omc, T *omd, int *err, hipStream_t st)
+hipError_t launch_init_omega(const T *omega0, int p, int Gr, int Gc, int NR, T *omp, T *omdp,
+                             int *err, hipStream_t st)
 {
     const Circle C = Circle::make(p);
-    hipLaunchKernelGGL(init_omega_kernel<T>, dim3(grid_for((long long)C.m * C.H + p)),
-                       dim3(kThreads), 0, st, omega0, p, omc, omd, err);
+    const long long total = (long long)Gr * Gc * NR * (C.m + 1);
+    hipLaunchKernelGGL(init_omega_kernel<T>, dim3(grid_for(total, 8192)), dim3(kThreads), 0, st,
+                       omega0, p, Gr, Gc, NR, omp, omdp, err);
     return hipGetLastError();
 }
 
@@ -215,28 +251,32 @@ hipError_t launch_clear(unsigned *flags, int nflags, unsigned long long *red, in
 }
 
 template <typename T>
-hipError_t launch_init_publish(const T *W, int p, T *pub, T *pubd, hipStream_t st)
+hipError_t launch_init_publish(const T *W, int p, int Gr, int NR, T *pc, T *pd, hipStream_t st)
 {
-    hipLaunchKernelGGL(init_publish_kernel<T>, dim3(grid_for(p)), dim3(kThreads), 0, st, W, p, pub,
-                       pubd);
+    const Circle C = Circle::make(p);
+    const long long PS = (long long)Gr * NR;
+    hipLaunchKernelGGL(init_publish_kernel<T>, dim3(grid_for(2ll * C.m * PS + 2 * PS, 8192)),
+                       dim3(kThreads), 0, st, W, p, Gr, NR, pc, pd);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_finalize(const T *omc, const T *omd, const T *W, int p, T lam, T *omega,
-                           double *acc, unsigned long long *nnz, int *err, hipStream_t st)
+hipError_t launch_finalize(const T *omp, const T *omdp, int Gr, int Gc, int NR, const T *W, int p,
+                           T lam, T *omega, double *acc, unsigned long long *nnz, int *err,
+                           hipStream_t st)
 {
     hipLaunchKernelGGL(finalize_kernel<T>, dim3(grid_for((long long)p * p, 2048)), dim3(kThreads),
-                       0, st, omc, omd, W, p, lam, omega, acc, nnz, err);
+                       0, st, omp, omdp, Gr, Gc, NR, W, p, lam, omega, acc, nnz, err);
     return hipGetLastError();
 }
 
 #define CONCORD_SUPPORT_INST(T)                                                                  \
     template hipError_t launch_check_copy<T>(const T *, int, T *, bool, T *, int *, hipStream_t); \
-    template hipError_t launch_init_omega<T>(const T *, int, T *, T *, int *, hipStream_t);      \
-    template hipError_t launch_init_publish<T>(const T *, int, T *, T *, hipStream_t);          \
-    template hipError_t launch_finalize<T>(const T *, const T *, const T *, int, T, T *,         \
-                                           double *, unsigned long long *, int *, hipStream_t);
+    template hipError_t launch_init_omega<T>(const T *, int, int, int, int, T *, T *, int *,     \
+                                             hipStream_t);                                       \
+    template hipError_t launch_init_publish<T>(const T *, int, int, int, T *, T *, hipStream_t); \
+    template hipError_t launch_finalize<T>(const T *, const T *, int, int, int, const T *, int, T, \
+                                           T *, double *, unsigned long long *, int *, hipStream_t);
 
 CONCORD_SUPPORT_INST(float)
 CONCORD_SUPPORT_INST(double)

@@ -13,13 +13,15 @@ template <typename T>
 hipError_t launch_check_copy(const T *S, int p, T *W, bool copy_w, T *sd, int *err,
                              hipStream_t st);
 template <typename T>
-hipError_t launch_init_omega(const T *omega0, int p, T *omc, T *omd, int *err, hipStream_t st);
+hipError_t launch_init_omega(const T *omega0, int p, int Gr, int Gc, int NR, T *omp, T *omdp,
+                             int *err, hipStream_t st);
 hipError_t launch_clear(unsigned *flags, int nflags, unsigned long long *red, int nred, int *out,
                         int nout, double *acc, int nacc, hipStream_t st);
 template <typename T>
-hipError_t launch_init_publish(const T *W, int p, T *pub, T *pubd, hipStream_t st);
+hipError_t launch_init_publish(const T *W, int p, int Gr, int NR, T *pc, T *pd, hipStream_t st);
 template <typename T>
-hipError_t launch_finalize(const T *omc, const T *omd, const T *W, int p, T lam, T *omega,
-                           double *acc, unsigned long long *nnz, int *err, hipStream_t st);
+hipError_t launch_finalize(const T *omp, const T *omdp, int Gr, int Gc, int NR, const T *W, int p,
+                           T lam, T *omega, double *acc, unsigned long long *nnz, int *err,
+                           hipStream_t st);
 
 }  // namespace concord

@@ -7,30 +7,36 @@
 // omega_ij = omega_ji by d changes only rows i and j of W: W_i. += d S_j. and
 // W_j. += d S_i..  For the diagonal step, eq. (2)'s sum is
 // c_i = W_ii - S_ii omega_ii, and changing omega_ii by d gives W_i. += d S_i..
-// So each pair costs O(1) to evaluate plus an axpy of its two rows when it
-// moves, instead of two length-p sums.
+// So each pair costs O(1) to evaluate plus a row update when it moves,
+// instead of two length-p sums.
 //
-// Work split.  Workgroup (a, b), a < Gr, b < Gc, owns rows i = a (mod Gr) of W
-// restricted to column slice b; its block stays in LDS when it fits, else in
-// HBM (touched only by this workgroup, so ordinary cached accesses).  Per
-// colour step every workgroup:
-//   A. reads, for each own row i with partner j, the two published numerator
-//      entries W_ij, W_ji and omega_ij, and evaluates eq. (3) (and, after the
-//      last colour, eq. (2)).  Every workgroup of rows i's group and of j's
-//      group evaluates the same pair from the same bits, so all agree on d.
-//   B. publishes, for the next colour's partner k of row i when column k lies
-//      in its slice, the updated W_ik (the row's entry that the next colour
-//      reads), plus W_ii ahead of the last colour.
-//   C. signals the grid barrier,
-//   D. applies its share of the row axpys while the barrier settles,
-//   E. waits for the barrier.
-// The diagonal step needs no barrier of its own: every workgroup of row i's
-// group recomputes c_i from the published W_ii.  So one sweep is m barriers.
+// Work split.  Workgroup g = a * Gc + b owns rows i = a (mod Gr) of W
+// restricted to column slice b (in LDS when the block fits, else in HBM where
+// only this workgroup touches it).  It keeps its own copy of omega for those
+// rows (every workgroup of a row group computes the same changes from the
+// same bits, so the copies stay identical).
+//
+// Synchronisation.  Colour r of a sweep needs, for pair (i, j), the entries
+// W_ij and W_ji as they stand after colour r - 1.  The workgroup owning
+// (row i, column j) publishes W_ij into a slot of `pc` as soon as its colour
+// r - 1 change is known; the readers poll that slot until the sentinel is
+// gone.  So colours are ordered by point-to-point waits, not by grid
+// barriers; one grid barrier per sweep carries the convergence test.  The
+// diagonal step is folded into the last colour: W_ii is published one colour
+// early (slot `pd`) and every workgroup of the row group finishes c_i itself.
+//
+// Deferred row updates.  A change of row i only has to reach W_ik by the time
+// W_ik is next published.  Each row keeps a list of pending (source row,
+// change) updates; a published entry is the stored W_ik with the pending
+// updates applied on the fly (same fused multiply-adds, same order), and the
+// whole row segment is rewritten only when the list fills.  The results are
+// bit-identical to applying every update at once; HBM traffic for W drops by
+// the list depth.
 //
 // Convergence.  Each entry of Omega changes exactly once per sweep, so
-// |Omega^(t) - Omega^(t-1)|_inf is the max |d| over the sweep; it is reduced
-// with one atomic max per workgroup per sweep and read by every workgroup
-// after the next barrier, so all agree on when to stop.
+// |Omega^(t) - Omega^(t-1)|_inf is the max |change| over the sweep; it is
+// reduced with one atomic max per workgroup, and read by every workgroup
+// after the sweep's grid barrier, so all agree on when to stop.
 #include "device_common.hpp"
 #include "schedule.hpp"
 #include "sweep.hpp"
@@ -39,48 +45,46 @@ namespace concord {
 
 namespace {
 
-// Grid barrier: workgroup g stores the epoch into flags[g]; wave 0 of every
+constexpr int kMaxDepth = 8;  // longest pending list (registers hold one S value per entry)
+
+// Sweep barrier: workgroup g stores the epoch into flags[g]; wave 0 of every
 // workgroup polls all flags.  Bounded: after spin_limit polls (or when any
 // workgroup has raised the abort word) it gives up and reports failure.
 template <typename T>
-__device__ __forceinline__ void grid_arrive(const SweepParams<T> &P, unsigned epoch)
+__device__ bool sweep_barrier(const SweepParams<T> &P, unsigned epoch, int *s_fail)
 {
     wait_stores();
     __syncthreads();
-    if (gridDim.x > 1 && threadIdx.x == 0)
-        st_dev(&P.flags[blockIdx.x], epoch);
-}
-
-template <typename T>
-__device__ __forceinline__ bool grid_wait(const SweepParams<T> &P, unsigned epoch, int *s_fail)
-{
-    if (gridDim.x > 1 && threadIdx.x < 64) {
-        const int G = gridDim.x;
-        long long spins = 0;
-        for (;;) {
-            int ok = 1;
-            for (int g = threadIdx.x; g < G; g += 64)
-                ok &= (ld_dev(&P.flags[g]) >= epoch) ? 1 : 0;
-            if (__all(ok))
-                break;
-            if (++spins > P.spin_limit || ld_dev(&P.out[3]) != 0) {
-                if (threadIdx.x == 0) {
-                    st_dev(&P.out[3], 1);
-                    *s_fail = 1;
+    const int G = gridDim.x;
+    if (G > 1) {
+        if (threadIdx.x == 0)
+            st_dev(&P.flags[blockIdx.x], epoch);
+        if (threadIdx.x < 64) {
+            long long spins = 0;
+            for (;;) {
+                int ok = 1;
+                for (int g = threadIdx.x; g < G; g += 64)
+                    ok &= (ld_dev(&P.flags[g]) >= epoch) ? 1 : 0;
+                if (__all(ok))
+                    break;
+                if (++spins > P.spin_limit || ld_dev(&P.out[3]) != 0) {
+                    if (threadIdx.x == 0) {
+                        st_dev(&P.out[3], 1);
+                        *s_fail = 1;
+                    }
+                    break;
                 }
-                break;
+                __builtin_amdgcn_s_sleep(1);
             }
-            __builtin_amdgcn_s_sleep(1);
         }
+        __syncthreads();
     }
-    __syncthreads();
     return *s_fail == 0;
 }
 
 template <typename T>
 __device__ __forceinline__ T block_max(T v, T *scratch)
 {
-    // wave-level max via shuffles, then across waves through LDS
     for (int off = 32; off > 0; off >>= 1) {
         T o = __shfl_xor(v, off, 64);
         v = (o > v || o != o) ? o : v;
@@ -111,228 +115,442 @@ __device__ __forceinline__ unsigned block_sum(unsigned v, unsigned *scratch)
     return r;
 }
 
-}  // namespace
+template <typename T>
+__device__ __forceinline__ T as_value(typename Sentinel<T>::U u)
+{
+    T v;
+    __builtin_memcpy(&v, &u, sizeof(T));
+    return v;
+}
+
+// Rewrites the segments of the listed rows with their pending updates:
+// W_ic <- fma(d_e, S_{src_e, c}, ...) in list order, for c in the slice.
+// Work is cut into (row, 128-column chunk) units dealt out to the waves; each
+// lane handles two columns so that 2 (n + 1) loads are in flight per lane.
+template <typename T, bool WLDS>
+__device__ void flush_rows(const int *rows, int nrows, const int *pj, const T *pdl,
+                           const int *np, int D, int a, int Gr, int p, int c0, int nc,
+                           const T *__restrict__ S, T *__restrict__ Wg, T *wblk)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int chunks = (nc + 127) >> 7;
+    const int units = nrows * chunks;
+    for (int u = wv; u < units; u += nw) {
+        const int fr = u / chunks, ch = u - fr * chunks;
+        const int k = rows[fr];
+        const int i = a + k * Gr;
+        const int n = np[k];
+        const int cA = ch * 128 + lane, cB = cA + 64;
+        const bool okA = cA < nc, okB = cB < nc;
+        T sa[kMaxDepth], sb[kMaxDepth];
+#pragma unroll
+        for (int e = 0; e < kMaxDepth; ++e) {
+            if (e < n) {
+                const T *row = S + (size_t)pj[k * D + e] * p + c0;
+                sa[e] = okA ? row[cA] : T(0);
+                sb[e] = okB ? row[cB] : T(0);
+            }
+        }
+        T *wa = WLDS ? &wblk[(size_t)k * nc] : &Wg[(size_t)i * p + c0];
+        T va = okA ? wa[cA] : T(0), vb = okB ? wa[cB] : T(0);
+#pragma unroll
+        for (int e = 0; e < kMaxDepth; ++e) {
+            if (e < n) {
+                const T d = pdl[k * D + e];
+                va = fma(d, sa[e], va);
+                vb = fma(d, sb[e], vb);
+            }
+        }
+        if (okA)
+            wa[cA] = va;
+        if (okB)
+            wa[cB] = vb;
+    }
+}
+
+// Operands of one row's next colour step that do not depend on that step's
+// change, loaded one step ahead so that their latency overlaps the previous
+// step's synchronisation and row rewrites.
+template <typename T>
+struct RowNext {
+    int j;        // partner in the step (-1: idle)
+    int kn;       // column published by the step (-1: none in this slice)
+    int n;        // pending entries the published value folds in
+    bool last;    // the step is the last colour (diagonal step follows)
+    bool pubd;    // the step publishes W_ii for the following last colour
+    T w, od, s_ji, wb, s_jn, s_in;
+    T sv[kMaxDepth];
+};
 
 template <typename T, bool WLDS>
-__global__ void __launch_bounds__(1024) pcd_sweep_kernel(SweepParams<T> P)
+__device__ __forceinline__ void load_next(RowNext<T> &x, const Circle &C, int r1, int i, int k,
+                                          int n, const int *pj, int D, int NR, int p, int c0,
+                                          int c1, int nc, const T *__restrict__ S,
+                                          const T *__restrict__ Wg, const T *wblk,
+                                          const T *__restrict__ omp, const T *__restrict__ omdp)
 {
+    const int m = C.m;
+    const int rn1 = (r1 + 1 == m) ? 0 : r1 + 1;
+    x.j = C.partner(r1, i);
+    const int kn = C.partner(rn1, i);
+    x.kn = (kn >= c0 && kn < c1) ? kn : -1;
+    x.last = (r1 == m - 1);
+    x.pubd = (rn1 == m - 1) && i >= c0 && i < c1;
+    x.n = n;
+    x.w = (x.j >= 0) ? omp[(size_t)r1 * NR + k] : T(0);
+    x.od = x.last ? omdp[k] : T(0);
+    x.s_ji = (x.j >= 0 && (x.last || x.pubd)) ? S[(size_t)x.j * p + i] : T(0);
+    if (x.kn >= 0) {
+        x.wb = WLDS ? wblk[(size_t)k * nc + (x.kn - c0)] : Wg[(size_t)i * p + x.kn];
+#pragma unroll
+        for (int e = 0; e < kMaxDepth; ++e)
+            if (e < n)
+                x.sv[e] = S[(size_t)pj[k * D + e] * p + x.kn];
+        x.s_jn = (x.j >= 0) ? S[(size_t)x.j * p + x.kn] : T(0);
+        x.s_in = x.last ? S[(size_t)i * p + x.kn] : T(0);
+    }
+}
+
+}  // namespace
+
+template <typename T, bool WLDS, int RPT>
+__global__ void __launch_bounds__(512) pcd_sweep_kernel(SweepParams<T> P)
+{
+    using U = typename Sentinel<T>::U;
+    constexpr U SENT = Sentinel<T>::bits;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const Circle C = Circle::make(P.p);
-    const int p = P.p, m = C.m, H = C.H;
+    const int p = P.p, m = C.m;
     const int tid = threadIdx.x, nthr = blockDim.x;
-    const int a = blockIdx.x / P.Gc, b = blockIdx.x % P.Gc;
-    const int nr = (a < p) ? (p - a + P.Gr - 1) / P.Gr : 0;
+    const int g = blockIdx.x, G = gridDim.x;
+    const int a = g / P.Gc, b = g % P.Gc;
+    const int Gr = P.Gr;
+    const int nr = (a < p) ? (p - a + Gr - 1) / Gr : 0;
     const int c0 = slice_lo(b, P.Gc, p), c1 = slice_lo(b + 1, P.Gc, p);
     const int nc = c1 - c0;
-    const int NR = P.nr_max;
+    const int NR = P.nr_max, D = P.depth;
+    const int PS = Gr * NR;  // published slots per colour; row i sits at (i mod Gr) * NR + i / Gr
 
     // LDS carve-up (sizes fixed by the host in sweep_lds_bytes).
-    T *rdel = reinterpret_cast<T *>(smem_raw);  // change of omega_{i, partner}
-    T *rdd = rdel + NR;                         // change of omega_ii (last colour)
-    T *rpend = rdd + NR;                        // new omega_{i, partner}, written one step late
-    T *rpendd = rpend + NR;                     // new omega_ii, written one step late
-    T *wred = rpendd + NR;                      // 16 wave partials
+    T *pdl = reinterpret_cast<T *>(smem_raw);   // pending changes, NR x D
+    T *wred = pdl + (size_t)NR * D;             // 16 wave partials
     T *wblk = wred + 16;                        // W block (LDS variant): NR x nc_max
-    int *rj = reinterpret_cast<int *>(wblk + (WLDS ? (size_t)NR * P.nc_max : 0));
-    int *act = rj + NR;                         // active row list
-    int *nact = act + NR;                       // [2] counters by step parity
-    int *s_fail = nact + 2;
+    int *pj = reinterpret_cast<int *>(wblk + (WLDS ? (size_t)NR * P.nc_max : 0));  // NR x D sources
+    int *np = pj + (size_t)NR * D;              // pending count per row
+    int *flist = np + NR;                       // rows to rewrite this step
+    int *nflush = flist + NR;                   // [3] counters, by step mod 3
+    int *s_fail = nflush + 3;
     unsigned *ured = reinterpret_cast<unsigned *>(s_fail + 1);  // 16 wave partials
 
     const T *__restrict__ S = P.S;
+    const T *__restrict__ sd = P.sd;
     T *__restrict__ Wg = P.W;
+    T *__restrict__ omp = P.omp + (size_t)g * m * NR;
+    T *__restrict__ omdp = P.omdp + (size_t)g * NR;
 
+    for (int k = tid; k < NR; k += nthr)
+        np[k] = 0;
     if (tid == 0) {
-        nact[0] = 0;
-        nact[1] = 0;
+        nflush[0] = 0;
+        nflush[1] = 0;
+        nflush[2] = 0;
         *s_fail = 0;
     }
     if (WLDS) {
         for (long e = tid; e < (long)nr * nc; e += nthr) {
-            int k = (int)(e / nc), c = (int)(e - (long)k * nc);
-            wblk[(size_t)k * nc + c] = Wg[(size_t)(a + k * P.Gr) * p + c0 + c];
+            const int k = (int)(e / nc), c = (int)(e - (long)k * nc);
+            wblk[(size_t)k * nc + c] = Wg[(size_t)(a + k * Gr) * p + c0 + c];
         }
     }
     __syncthreads();
 
     T dloc = T(0), gloc = T(0);
     unsigned moved = 0, moved_d = 0;  // pairs / diagonals that changed (counted once each)
-    int t = 0, r = 0, converged = 0, failed = 0;
-    unsigned long long s = 0;  // global colour-step counter
+    int t = 0, converged = 0, failed = 0;
+    bool flushed[RPT];
+    RowNext<T> nx[RPT];
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) {
+        flushed[u] = false;
+        const int k = tid + u * nthr;
+        if (k < nr)
+            load_next<T, WLDS>(nx[u], C, 0, a + k * Gr, k, 0, pj, D, NR, p, c0, c1, nc, S, Wg,
+                               wblk, omp, omdp);
+    }
+    unsigned step = 0;
 
     // A set-up kernel that found bad input leaves its bits in out[4]; then
     // every workgroup skips the sweeps (the same word is read by all).
     const bool run = ld_dev(&P.out[4]) == 0;
 
     while (run) {
-        const int par = (int)(s & 1);
-        const bool last = (r == m - 1);
-        const int tcur = (int)(s / (unsigned long long)m);
-        if (tid == 0)
-            nact[par ^ 1] = 0;
-
-        // ---- A. evaluate eq. (3) for every own row (and eq. (2) after the last colour)
-        for (int k = tid; k < nr; k += nthr) {
-            const int i = a + k * P.Gr;
-            const int j = C.partner(r, i);
-            T del = T(0), dd = T(0);
-            if (j >= 0) {
-                const int lo = i < j ? i : j, hi = i < j ? j : i;
-                const T wlo = ld_dev(&P.pub[(size_t)par * p + lo]);
-                const T whi = ld_dev(&P.pub[(size_t)par * p + hi]);
-                const T w = ld_dev(&P.omc[(size_t)r * H + C.slot(r, i)]);
-                const T sden = P.sd[lo] + P.sd[hi];
-                const T bnum = fma(-sden, w, wlo + whi);
-                const T wn = soft_threshold(-bnum, P.lam) / sden;
-                del = wn - w;
-                rpend[k] = wn;
-            }
-            if (last) {
-                T wii = ld_dev(&P.pubd[(size_t)(tcur & 1) * p + i]);
-                if (j >= 0 && del != T(0))
-                    wii = fma(del, S[(size_t)j * p + i], wii);
-                const T od = ld_dev(&P.omd[i]);
-                const T sii = P.sd[i];
-                const T c = fma(-sii, od, wii);
-                const T disc = sqrt(fma(c, c, T(4) * sii));
-                // eq. (2); for c >= 0 the same root is 2 / (c + disc) without cancellation.
-                const T on = (c >= T(0)) ? T(2) / (c + disc) : (disc - c) / (T(2) * sii);
-                dd = on - od;
-                rpendd[k] = on;
-                gloc = (on > gloc || on != on) ? on : gloc;
-            }
-            rj[k] = j;
-            rdel[k] = del;
-            rdd[k] = dd;
-            if (b == 0) {
-                moved += (j > i && del != T(0)) ? 1u : 0u;
-                moved_d += (dd != T(0)) ? 1u : 0u;
-            }
-            const T ad = fabs(del) > fabs(dd) ? fabs(del) : fabs(dd);
-            dloc = (ad > dloc || ad != ad) ? ad : dloc;
-            if (del != T(0) || dd != T(0)) {
-                int slot = atomicAdd(&nact[par], 1);
-                act[slot] = k;
+        const int cur = t & 1, nxt = cur ^ 1;
+        if (t >= 1) {
+            // Reset to the sentinel the slots that sweep t + 1 reads after
+            // they are written within that sweep: colours >= 1 of buffer nxt,
+            // and pd[nxt] when the diagonal entry is published in-sweep (m >= 2).
+            // Their last readers finished in sweep t - 1.
+            const long long E = (long long)(m - 1) * PS + (m >= 2 ? PS : 0);
+            const long long e0 = E * g / G, e1 = E * (g + 1) / G;
+            U *pcb = reinterpret_cast<U *>(P.pc + ((size_t)nxt * m + 1) * PS);
+            U *pdb = reinterpret_cast<U *>(P.pd + (size_t)nxt * PS);
+            for (long long e = e0 + tid; e < e1; e += nthr) {
+                if (e < (long long)(m - 1) * PS)
+                    st_dev(&pcb[e], SENT);
+                else
+                    st_dev(&pdb[e - (long long)(m - 1) * PS], SENT);
             }
         }
 
-        // ---- B. publish the next step's numerator entries of own rows
-        const int rn = last ? 0 : r + 1;
-        const int parn = par ^ 1;
-        const int tnext = (int)((s + 1) / (unsigned long long)m);
-        for (int k = tid; k < nr; k += nthr) {
-            const int i = a + k * P.Gr;
-            const int j = rj[k];
-            const T del = rdel[k], dd = rdd[k];
-            const int kn = C.partner(rn, i);
-            if (kn >= c0 && kn < c1) {
-                T v = WLDS ? wblk[(size_t)k * nc + (kn - c0)] : Wg[(size_t)i * p + kn];
-                if (del != T(0))
-                    v = fma(del, S[(size_t)j * p + kn], v);
-                if (dd != T(0))
-                    v = fma(dd, S[(size_t)i * p + kn], v);
-                st_dev(&P.pub[(size_t)parn * p + i], v);
-            }
-            if (rn == m - 1 && i >= c0 && i < c1) {
-                T v = WLDS ? wblk[(size_t)k * nc + (i - c0)] : Wg[(size_t)i * p + i];
-                if (del != T(0))
-                    v = fma(del, S[(size_t)j * p + i], v);
-                if (dd != T(0))
-                    v = fma(dd, S[(size_t)i * p + i], v);
-                st_dev(&P.pubd[(size_t)(tnext & 1) * p + i], v);
-            }
-        }
+        for (int r = 0; r < m && !failed; ++r) {
+            const bool last = (r == m - 1);
+            const int rn = last ? 0 : r + 1;
+            const int bufn = last ? nxt : cur;   // buffer of the next colour step
+            const int s3 = (int)(step % 3u);
+            const U *pcu = reinterpret_cast<const U *>(P.pc + ((size_t)cur * m + r) * PS);
+            const U *pdu = reinterpret_cast<const U *>(P.pd + (size_t)cur * PS);
+            T *pcn = P.pc + ((size_t)bufn * m + rn) * PS;
+            // The next step reads pd when it is the last colour; the buffer
+            // is that step's sweep.
+            T *pdn = P.pd + (size_t)(last ? nxt : cur) * PS;
+            int lfail = 0, marked = 0;
+            // optional per-step timestamps (100 MHz clock): start, rows done, rewrites done
+            unsigned long long *ts =
+                (P.tstamp && tid == 0 && step < (unsigned)P.tstamp_steps)
+                    ? P.tstamp + ((size_t)g * P.tstamp_steps + step) * 3
+                    : nullptr;
+            if (ts)
+                ts[0] = __builtin_amdgcn_s_memrealtime();
 
-        if (last) {
-            const T dm = block_max(dloc, wred);
-            const T gm = block_max(gloc, wred);
-            const unsigned mv = block_sum(moved, ured);
-            const unsigned mvd = block_sum(moved_d, ured);
-            if (tid == 0) {
-                unsigned long long *rt = P.red + 4 * (size_t)tcur;
-                __hip_atomic_fetch_max(&rt[0], ord_bits(dm), __ATOMIC_RELAXED,
+#pragma unroll
+            for (int u = 0; u < RPT; ++u) {
+                const int k = tid + u * nthr;
+                if (k >= nr || lfail)
+                    continue;
+                const int i = a + k * Gr;
+                const RowNext<T> &x = nx[u];
+                const int j = x.j;
+
+                // ---- stored entries plus pending updates, for what this step publishes
+                T vpre = T(0), vdpre = T(0);
+                if (x.kn >= 0) {
+                    vpre = x.wb;
+#pragma unroll
+                    for (int e = 0; e < kMaxDepth; ++e)
+                        if (e < x.n)
+                            vpre = fma(pdl[k * D + e], x.sv[e], vpre);
+                }
+                if (flushed[u]) {
+                    np[k] = 0;
+                    flushed[u] = false;
+                }
+                const int n0 = np[k];
+                if (x.pubd) {
+                    // once per sweep: W_ii with the pending updates, loaded here
+                    vdpre = WLDS ? wblk[(size_t)k * nc + (i - c0)] : Wg[(size_t)i * p + i];
+                    for (int e = 0; e < n0; ++e)
+                        vdpre = fma(pdl[k * D + e], S[(size_t)pj[k * D + e] * p + i], vdpre);
+                }
+
+                // ---- wait for the published numerator entries of this colour
+                U blo = 0, bhi = 0, bd = 0;
+                {
+                    // slots of row i (own, contiguous over k) and of its partner
+                    const int si = a * NR + k;
+                    const int sj = (j >= 0) ? (j % Gr) * NR + j / Gr : 0;
+                    const int lo = (j >= 0 && j < i) ? sj : si, hi = (j >= 0 && j < i) ? si : sj;
+                    const bool poll_d = last && m >= 2;
+                    long long spins = 0;
+                    for (;;) {
+                        bool ok = true;
+                        if (j >= 0) {
+                            blo = ld_dev(&pcu[lo]);
+                            bhi = ld_dev(&pcu[hi]);
+                            ok = (blo != SENT) && (bhi != SENT);
+                        }
+                        if (last) {
+                            bd = ld_dev(&pdu[si]);
+                            ok = ok && (!poll_d || bd != SENT);
+                        }
+                        if (ok)
+                            break;
+                        ++spins;
+                        if (spins > P.spin_limit ||
+                            ((spins & 255) == 0 && ld_dev(&P.out[3]) != 0)) {
+                            st_dev(&P.out[3], 1);
+                            lfail = 1;
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(1);
+                    }
+                }
+                if (lfail) {
+                    *s_fail = 1;
+                    continue;
+                }
+
+                // ---- eq. (3) for the pair, eq. (2) after the last colour
+                T del = T(0), dd = T(0);
+                if (j >= 0) {
+                    const int lo = j < i ? j : i, hi = j < i ? i : j;
+                    const T sden = sd[lo] + sd[hi];
+                    const T bnum = fma(-sden, x.w, as_value<T>(blo) + as_value<T>(bhi));
+                    const T wn = soft_threshold(-bnum, P.lam) / sden;
+                    del = wn - x.w;
+                    if (del != T(0))
+                        omp[(size_t)r * NR + k] = wn;
+                }
+                if (last) {
+                    T wii = as_value<T>(bd);
+                    if (del != T(0))
+                        wii = fma(del, x.s_ji, wii);
+                    const T sii = sd[i];
+                    const T c = fma(-sii, x.od, wii);
+                    const T disc = sqrt(fma(c, c, T(4) * sii));
+                    // eq. (2); for c >= 0 the same root is 2 / (c + disc) without cancellation.
+                    const T on = (c >= T(0)) ? T(2) / (c + disc) : (disc - c) / (T(2) * sii);
+                    dd = on - x.od;
+                    if (dd != T(0))
+                        omdp[k] = on;
+                    gloc = (on > gloc || on != on) ? on : gloc;
+                }
+
+                // ---- record the changes as pending updates of row i
+                int n = n0;
+                if (del != T(0)) {
+                    pj[k * D + n] = j;
+                    pdl[k * D + n] = del;
+                    ++n;
+                }
+                if (dd != T(0)) {
+                    pj[k * D + n] = i;
+                    pdl[k * D + n] = dd;
+                    ++n;
+                }
+                np[k] = n;
+
+                // ---- publish what the next colour reads from row i
+                if (x.kn >= 0) {
+                    T v = vpre;
+                    if (del != T(0))
+                        v = fma(del, x.s_jn, v);
+                    if (dd != T(0))
+                        v = fma(dd, x.s_in, v);
+                    st_dev(&pcn[a * NR + k], v);
+                }
+                if (x.pubd) {
+                    T v = vdpre;
+                    if (del != T(0))
+                        v = fma(del, x.s_ji, v);
+                    if (dd != T(0))
+                        v = fma(dd, sd[i], v);
+                    st_dev(&pdn[a * NR + k], v);
+                }
+                if (n > D - 2) {
+                    flist[atomicAdd(&nflush[s3], 1)] = k;
+                    flushed[u] = true;
+                    marked = 1;
+                }
+                const T ad = fabs(del) > fabs(dd) ? fabs(del) : fabs(dd);
+                dloc = (ad > dloc || ad != ad) ? ad : dloc;
+                if (b == 0) {
+                    moved += (j > i && del != T(0)) ? 1u : 0u;
+                    moved_d += (dd != T(0)) ? 1u : 0u;
+                }
+
+                // ---- operands of the row's next step.  The stored W entry is
+                // read before this step's rewrites (they start after the
+                // workgroup barrier below), so it is folded with all n entries.
+                load_next<T, WLDS>(nx[u], C, rn, i, k, n, pj, D, NR, p, c0, c1, nc, S, Wg, wblk,
+                                   omp, omdp);
+            }
+
+            // ---- every row of the step is done; rewrite the rows whose lists are full
+            const int any = __syncthreads_or(lfail | marked);
+            if (tid == 0)
+                nflush[(s3 + 2) % 3] = 0;  // counter of the previous step, read by all by now
+            if (ts)
+                ts[1] = __builtin_amdgcn_s_memrealtime();
+            if (any) {
+                if (*s_fail) {
+                    failed = 1;
+                    break;
+                }
+                const int nf = nflush[s3];
+                if (nf > 0) {
+                    flush_rows<T, WLDS>(flist, nf, pj, pdl, np, D, a, Gr, p, c0, nc, S, Wg, wblk);
+                    __syncthreads();
+                }
+            }
+            if (ts)
+                ts[2] = __builtin_amdgcn_s_memrealtime();
+            ++step;
+        }
+        if (failed)
+            break;
+
+        // ---- end of sweep t: reductions, then the sweep barrier
+        const T dm = block_max(dloc, wred);
+        const T gm = block_max(gloc, wred);
+        const unsigned mv = block_sum(moved, ured);
+        const unsigned mvd = block_sum(moved_d, ured);
+        if (tid == 0) {
+            unsigned long long *rt = P.red + 4 * (size_t)t;
+            __hip_atomic_fetch_max(&rt[0], ord_bits(dm), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_max(&rt[1], ord_bits(gm), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (mv)
+                __hip_atomic_fetch_add(&rt[2], (unsigned long long)mv, __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
-                __hip_atomic_fetch_max(&rt[1], ord_bits(gm), __ATOMIC_RELAXED,
+            if (mvd)
+                __hip_atomic_fetch_add(&rt[3], (unsigned long long)mvd, __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
-                if (mv)
-                    __hip_atomic_fetch_add(&rt[2], (unsigned long long)mv, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-                if (mvd)
-                    __hip_atomic_fetch_add(&rt[3], (unsigned long long)mvd, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-            }
-            dloc = T(0);
-            gloc = T(0);
-            moved = 0;
-            moved_d = 0;
         }
-
-        // ---- C. signal
-        const unsigned epoch = (unsigned)(s + 1);
-        grid_arrive(P, epoch);
-
-        // ---- D. row axpys on the owned block: W_i. += d S_j. (+ d_ii S_i.)
-        {
-            const int na = nact[par];
-            const long total = (long)na * nc;
-            for (long e = tid; e < total; e += nthr) {
-                const int ai = (int)(e / nc);
-                const int c = (int)(e - (long)ai * nc);
-                const int k = act[ai];
-                const int i = a + k * P.Gr;
-                const int j = rj[k];
-                const T del = rdel[k], dd = rdd[k];
-                T *wp = WLDS ? &wblk[(size_t)k * nc + c] : &Wg[(size_t)i * p + c0 + c];
-                T v = *wp;
-                if (del != T(0))
-                    v = fma(del, S[(size_t)j * p + c0 + c], v);
-                if (dd != T(0))
-                    v = fma(dd, S[(size_t)i * p + c0 + c], v);
-                *wp = v;
-            }
-        }
-
-        // ---- E. wait, then the deferred omega writes of this step
-        if (!grid_wait(P, epoch, s_fail)) {
+        dloc = T(0);
+        gloc = T(0);
+        moved = 0;
+        moved_d = 0;
+        if (!sweep_barrier(P, (unsigned)(t + 1), s_fail)) {
             failed = 1;
             break;
         }
-        if (b == 0) {
-            for (int k = tid; k < nr; k += nthr) {
-                const int i = a + k * P.Gr;
-                const int j = rj[k];
-                if (j > i)
-                    st_dev(&P.omc[(size_t)r * H + C.slot(r, i)], rpend[k]);
-                if (last)
-                    st_dev(&P.omd[i], rpendd[k]);
-            }
+        const T delta = from_ord(ld_dev(&P.red[4 * (size_t)t]), T(0));
+        const T gmax = from_ord(ld_dev(&P.red[4 * (size_t)t + 1]), T(0));
+        ++t;
+        T tol_eff = P.tol_coef * gmax;
+        tol_eff = tol_eff > P.tol ? tol_eff : P.tol;
+        if (delta < tol_eff) {
+            converged = 1;
+            break;
         }
-        ++s;
-        if (last) {
-            t = tcur + 1;
-            const T delta = from_ord(ld_dev(&P.red[4 * (size_t)tcur]), T(0));
-            const T gmax = from_ord(ld_dev(&P.red[4 * (size_t)tcur + 1]), T(0));
-            T tol_eff = P.tol_coef * gmax;
-            tol_eff = tol_eff > P.tol ? tol_eff : P.tol;
-            if (delta < tol_eff) {
-                converged = 1;
-                break;
-            }
-            if (t >= P.maxit)
-                break;
-        }
-        r = rn;
+        if (t >= P.maxit)
+            break;
     }
 
-    wait_stores();
-    if (WLDS) {
-        __syncthreads();
-        for (long e = tid; e < (long)nr * nc; e += nthr) {
-            int k = (int)(e / nc), c = (int)(e - (long)k * nc);
-            Wg[(size_t)(a + k * P.Gr) * p + c0 + c] = wblk[(size_t)k * nc + c];
+    // Apply every pending update so that the stored W is Omega S again.
+    __syncthreads();
+    if (tid == 0)
+        nflush[0] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) {
+        const int k = tid + u * nthr;
+        if (k < nr) {
+            if (flushed[u])
+                np[k] = 0;
+            if (np[k] > 0)
+                flist[atomicAdd(&nflush[0], 1)] = k;
         }
     }
-    if (blockIdx.x == 0 && tid == 0) {
+    __syncthreads();
+    flush_rows<T, WLDS>(flist, nflush[0], pj, pdl, np, D, a, Gr, p, c0, nc, S, Wg, wblk);
+    __syncthreads();
+    if (WLDS) {
+        for (long e = tid; e < (long)nr * nc; e += nthr) {
+            const int k = (int)(e / nc), c = (int)(e - (long)k * nc);
+            Wg[(size_t)(a + k * Gr) * p + c0 + c] = wblk[(size_t)k * nc + c];
+        }
+    }
+    if (g == 0 && tid == 0) {
         P.out[0] = t;
         P.out[1] = converged;
         P.out[2] = failed;
@@ -340,25 +558,36 @@ __global__ void __launch_bounds__(1024) pcd_sweep_kernel(SweepParams<T> P)
 }
 
 template <typename T>
-size_t sweep_lds_bytes(const SweepParams<T> &P, int threads)
+size_t sweep_lds_bytes(const SweepParams<T> &P)
 {
-    (void)threads;
-    size_t b = sizeof(T) * (4 * (size_t)P.nr_max + 16);
+    size_t bytes = sizeof(T) * ((size_t)P.nr_max * P.depth + 16);
     if (P.w_lds)
-        b += sizeof(T) * (size_t)P.nr_max * P.nc_max;
-    b += sizeof(int) * (2 * (size_t)P.nr_max + 3) + sizeof(unsigned) * 16;
-    return b;
+        bytes += sizeof(T) * (size_t)P.nr_max * P.nc_max;
+    bytes += sizeof(int) * ((size_t)P.nr_max * P.depth + 2 * (size_t)P.nr_max + 4);
+    bytes += sizeof(unsigned) * 16;
+    return bytes;
 }
+
+namespace {
+
+template <typename T, bool WLDS>
+const void *pick_kernel(int rpt)
+{
+    if (rpt <= 1)
+        return (const void *)pcd_sweep_kernel<T, WLDS, 1>;
+    return (const void *)pcd_sweep_kernel<T, WLDS, 2>;
+}
+
+}  // namespace
 
 template <typename T>
 hipError_t launch_sweep(const SweepParams<T> &P, int threads, hipStream_t stream)
 {
-    size_t lds = sweep_lds_bytes(P, threads);
+    const size_t lds = sweep_lds_bytes(P);
     const int G = P.Gr * P.Gc;
     SweepParams<T> arg = P;
     void *args[] = {&arg};
-    const void *fn = P.w_lds ? (const void *)pcd_sweep_kernel<T, true>
-                             : (const void *)pcd_sweep_kernel<T, false>;
+    const void *fn = P.w_lds ? pick_kernel<T, true>(P.rpt) : pick_kernel<T, false>(P.rpt);
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess)
         return e;
@@ -367,8 +596,8 @@ hipError_t launch_sweep(const SweepParams<T> &P, int threads, hipStream_t stream
     return hipLaunchCooperativeKernel(fn, dim3(G), dim3(threads), args, (unsigned)lds, stream);
 }
 
-template size_t sweep_lds_bytes<float>(const SweepParams<float> &, int);
-template size_t sweep_lds_bytes<double>(const SweepParams<double> &, int);
+template size_t sweep_lds_bytes<float>(const SweepParams<float> &);
+template size_t sweep_lds_bytes<double>(const SweepParams<double> &);
 template hipError_t launch_sweep<float>(const SweepParams<float> &, int, hipStream_t);
 template hipError_t launch_sweep<double>(const SweepParams<double> &, int, hipStream_t);
 

@@ -14,9 +14,12 @@ namespace concord {
 //         omega_{i, partner_r(i)} for the workgroup's k-th row i = a + k Gr
 //   omdp  per-workgroup diagonals: omdp[g * nr_max + k] = omega_ii
 //   sd    diag(S), p
-//   pc    published numerator entries, two sweep-parity buffers:
-//         pc[(buf * m + r) * p + i] = W_{i, partner_r(i)} as colour r reads it
-//   pd    pd[buf * p + i] = W_ii as the last colour reads it
+//   pc    published numerator entries, two sweep-parity buffers of m colours
+//         of PS = Gr * nr_max slots, row i at slot (i mod Gr) * nr_max + i / Gr
+//         (a row group's slots are contiguous, and so, up to one wrap, are the
+//         slots of its partners in any colour):
+//         pc[(buf * m + r) * PS + slot(i)] = W_{i, partner_r(i)} as colour r reads it
+//   pd    pd[buf * PS + slot(i)] = W_ii as the last colour reads it
 //   flags one sweep-barrier word per workgroup (epochs)
 //   red   per sweep t, 4 words: [4t] max |change| (bits), [4t+1] max omega_ii (bits),
 //         [4t+2] pairs that changed, [4t+3] diagonals that changed
@@ -48,6 +51,8 @@ struct SweepParams {
     T tol;
     T tol_coef;        // tol_eff = max(tol, tol_coef * max_i omega_ii)
     long long spin_limit;
+    unsigned long long *tstamp;  // optional: [G][tstamp_steps][3] device timestamps
+    int tstamp_steps;
 };
 
 // Column slice b of Gc over p columns: [slice_lo(b), slice_lo(b + 1)).

@@ -84,6 +84,9 @@ SHAPES = [
     dict(row_groups=2, col_slices=4, w_in_lds=2),
     dict(row_groups=16, col_slices=4, block_threads=256),
     dict(row_groups=64, col_slices=1),                # one row per workgroup
+    dict(row_groups=8, col_slices=2, w_in_lds=2, pending_depth=4),
+    dict(row_groups=4, col_slices=4, w_in_lds=2, pending_depth=8),
+    dict(row_groups=1, col_slices=3, block_threads=64, pending_depth=6),
 ]
 
 
@@ -125,6 +128,19 @@ def test_ragged_p_fp64(lib, p):
     if p >= 8:
         g2, i2 = _gpu_fit(lib, pr["S"], lam, tol, 2000, row_groups=min(p, 7), col_slices=3)
         assert np.array_equal(g2, got)
+        g3, i3 = _gpu_fit(lib, pr["S"], lam, tol, 2000, row_groups=3, col_slices=2,
+                          block_threads=64, w_in_lds=2, pending_depth=5)
+        assert np.array_equal(g3, got)
+
+
+@pytest.mark.parametrize("wl", [1, 2])
+def test_two_rows_per_thread(lib, wl):
+    # 100 rows in one row group on 64 threads: each thread carries two rows.
+    pr = _problem(2, p=100, n=150)
+    want, winfo, _ = _oracle(pr, 0.15, 1e-9, 2000)
+    got, ginfo = _gpu_fit(lib, pr["S"], 0.15, 1e-9, 2000, row_groups=1, col_slices=2,
+                          block_threads=64, w_in_lds=wl, pending_depth=3)
+    _assert_parity64(pr["S"], got, ginfo, want, winfo, 0.15)
 
 
 @pytest.mark.parametrize("p", [5, 64, 129, 257])
