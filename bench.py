@@ -72,6 +72,22 @@ def cpu_oracle_baseline(y, p: int, lam: float, elem: int, gpu_sweeps: int, bytes
     }
 
 
+def measured_traffic(p: int, n: int, lam: float, dtype: str):
+    """HBM bytes per sweep-kernel launch from the committed rocprofv3 counter
+    runs, or None when they were taken on another workload or kernel source."""
+    import hashlib
+    try:
+        rec = json.load(open(os.path.join(ROOT, "profiles", "pcd_sweep_traffic.json")))
+        src = open(os.path.join(ROOT, "paper_2106_09382_amd", "csrc", "sweep.hip"), "rb").read()
+    except (OSError, ValueError):
+        return None
+    if hashlib.sha256(src).hexdigest()[:16] != rec.get("sweep_hip_sha256_16"):
+        return None
+    if (p, n, lam, dtype) != (5000, 2000, 0.1, "f64"):
+        return None
+    return float(rec["bytes_per_launch"])
+
+
 def _cpu_model() -> str:
     try:
         for line in open("/proc/cpuinfo"):
@@ -201,7 +217,7 @@ def main() -> int:
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": measured_traffic(args.p, args.n, args.lam, args.dtype),
         },
     }
     if not args.no_cpu_baseline:
