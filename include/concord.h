@@ -87,6 +87,9 @@ typedef struct {
     uint64_t *device_timestamps;
     int32_t timestamp_steps;
     int32_t reserved;
+    /* Optional device p x p array (element type dt): receives the maintained
+     * product W = Omega S as the solve leaves it (for checks). */
+    void *w_out;
 } concord_options;
 
 /*
@@ -115,6 +118,61 @@ int concord_fit(concord_input kind, const void *X, int64_t n, int64_t p, double 
 int concord_fit_ex(concord_input kind, const void *X, int64_t n, int64_t p, double lambda,
                    double tol, int32_t maxit, concord_dtype dt, const void *omega0, void *omega,
                    concord_info *info, void *stream, const concord_options *opts);
+
+/* Launch options of the batched solver (all 0 = defaults). */
+typedef struct {
+    int32_t workgroups;     /* workgroups of one launch, <= compute units (0 = all) */
+    int32_t block_threads;  /* threads per workgroup, multiple of 64, <= 512 (0 = 512) */
+    int32_t pending_depth;  /* 2..8 row updates held before a row is rewritten (0 = 8) */
+    int32_t reserved;
+    /* Optional host array of B workgroup counts, one per problem (each at
+     * least ceil(p_b / (2 * block_threads)) and at most p_b, summing to at
+     * most `workgroups`): all problems then share one launch with these
+     * counts instead of the built-in plan.  NULL = built-in plan. */
+    const int32_t *problem_workgroups;
+} concord_batch_options;
+
+/*
+ * concord_fit_batched -- B independent CONCORD-PCD solves, each along a path
+ * of L values of lambda, in one persistent launch (more launches, in order,
+ * only when the problems' minimum workgroup counts exceed one launch).
+ * Problem b runs lambdas[b * L + 0], ..., lambdas[b * L + L - 1] in that
+ * order; the first starts from the identity (Algorithm 1's Omega^(0)), each
+ * later one from the Omega the previous one left (a warm start, as on a
+ * regularisation path).  Every lambda gets its own convergence test and
+ * maxit budget.
+ *   B          number of problems, >= 1
+ *   kind       as for concord_fit, for all problems
+ *   X          host array of B device pointers: S_b (p_b x p_b) or Y_b (n_b x p_b)
+ *   n          host array of B row counts (CONCORD_INPUT_Y; may be NULL for S)
+ *   p          host array of B sizes, each >= 1 (mixed sizes and parities allowed)
+ *   L          path length, >= 1 (L * maxit <= 2^24)
+ *   lambdas    host array B x L, each finite and >= 0 (any order; descending
+ *              is the usual path)
+ *   tol, maxit, dt   as for concord_fit
+ *   omega      host array of B x L device pointers: omega[b * L + l] receives
+ *              the p_b x p_b Omega at lambdas[b * L + l]
+ *   info       host array of B x L records (may be NULL): per lambda its
+ *              sweeps, status, delta, tol_eff, nnz_upper, objective, moved
+ *              counts and sweep_ms, the device time this lambda took;
+ *              elapsed_ms (the whole call) and gram_ms (the set-up before the
+ *              persistent launch) are those of the launch it ran in; row_groups
+ *              is the number of workgroups the problem had
+ * Returns the first negative per-solve status, else CONCORD_NOT_CONVERGED if
+ * any lambda stopped at maxit, else CONCORD_OK; info[].status has each one.
+ * Buffers of the batch must not overlap; the call returns after the stream's
+ * work completes.
+ */
+int concord_fit_batched(int32_t B, concord_input kind, const void *const *X, const int64_t *n,
+                        const int64_t *p, int32_t L, const double *lambdas, double tol,
+                        int32_t maxit, concord_dtype dt, void *const *omega, concord_info *info,
+                        void *stream);
+
+/* concord_fit_batched with launch options (opts may be NULL = defaults). */
+int concord_fit_batched_ex(int32_t B, concord_input kind, const void *const *X, const int64_t *n,
+                           const int64_t *p, int32_t L, const double *lambdas, double tol,
+                           int32_t maxit, concord_dtype dt, void *const *omega,
+                           concord_info *info, void *stream, const concord_batch_options *opts);
 
 /*
  * concord_gram -- S = Y^T Y / n (the T = X^T X of Algorithm 1's set-up, on

@@ -58,6 +58,17 @@ class ConcordOptions(ctypes.Structure):
         ("device_timestamps", ctypes.c_void_p),
         ("timestamp_steps", ctypes.c_int32),
         ("reserved", ctypes.c_int32),
+        ("w_out", ctypes.c_void_p),
+    ]
+
+
+class ConcordBatchOptions(ctypes.Structure):
+    _fields_ = [
+        ("workgroups", ctypes.c_int32),
+        ("block_threads", ctypes.c_int32),
+        ("pending_depth", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("problem_workgroups", ctypes.POINTER(ctypes.c_int32)),
     ]
 
 
@@ -90,6 +101,13 @@ def load(path: str = LIB_PATH):
     lib.concord_fit.restype = ctypes.c_int
     lib.concord_fit_ex.argtypes = lib.concord_fit.argtypes + [ctypes.POINTER(ConcordOptions)]
     lib.concord_fit_ex.restype = ctypes.c_int
+    lib.concord_fit_batched_ex.argtypes = [
+        i32, ctypes.c_int, ctypes.POINTER(vp), ctypes.POINTER(i64), ctypes.POINTER(i64), i32,
+        ctypes.POINTER(dbl), dbl, i32, ctypes.c_int, ctypes.POINTER(vp),
+        ctypes.POINTER(ConcordInfo), vp, ctypes.POINTER(ConcordBatchOptions)]
+    lib.concord_fit_batched_ex.restype = ctypes.c_int
+    lib.concord_fit_batched.argtypes = lib.concord_fit_batched_ex.argtypes[:-1]
+    lib.concord_fit_batched.restype = ctypes.c_int
     lib.concord_gram.argtypes = [vp, i64, i64, ctypes.c_int, vp, vp]
     lib.concord_gram.restype = ctypes.c_int
     lib.concord_schedule.argtypes = [i64, ctypes.POINTER(ctypes.c_int32)]
@@ -138,7 +156,7 @@ def fit(X: torch.Tensor, lam: float, tol: float = 1e-6, maxit: int = 500, *, kin
         omega0: torch.Tensor | None = None, out: torch.Tensor | None = None, stream=None,
         row_groups: int = 0, col_slices: int = 0, block_threads: int = 0, w_in_lds: int = 0,
         pending_depth: int = 0, trace: bool = False, check: bool = True,
-        timestamps: torch.Tensor | None = None):
+        timestamps: torch.Tensor | None = None, w_out: torch.Tensor | None = None):
     """One CONCORD-PCD solve.  X is S (p x p) or, with kind='Y', Y (n x p).
 
     Returns (omega, info dict); info['delta_trace'] holds every sweep's delta
@@ -171,7 +189,12 @@ def fit(X: torch.Tensor, lam: float, tol: float = 1e-6, maxit: int = 500, *, kin
         o0 = ctypes.c_void_p(omega0.data_ptr())
     info = ConcordInfo()
     opts = ConcordOptions(row_groups, col_slices, block_threads, w_in_lds, pending_depth, None,
-                          None, 0, 0)
+                          None, 0, 0, None)
+    if w_out is not None:
+        _check_dev(w_out, "w_out")
+        if w_out.dtype != X.dtype or tuple(w_out.shape) != (p, p):
+            raise ValueError("w_out must be p x p with X's dtype")
+        opts.w_out = w_out.data_ptr()
     if timestamps is not None:
         # int64 device tensor of shape (workgroups, steps, 3)
         _check_dev(timestamps, "timestamps")
@@ -192,6 +215,81 @@ def fit(X: torch.Tensor, lam: float, tol: float = 1e-6, maxit: int = 500, *, kin
     if check:
         _raise(code, "concord_fit")
     return out, d
+
+
+def fit_batched(Xs, lambdas, tol: float = 1e-6, maxit: int = 500, *, kind: str = "S",
+                outs=None, stream=None, workgroups: int = 0, block_threads: int = 0,
+                pending_depth: int = 0, problem_workgroups=None, check: bool = True):
+    """B independent solves along lambda paths in one persistent launch.
+
+    Xs: list of B device tensors (S_b, or Y_b with kind='Y'), one dtype.
+    lambdas: B x L nested sequence (or one length-L sequence for all).
+    Returns (omegas, infos, code): omegas[b][l] is the p_b x p_b Omega at
+    lambdas[b][l] (warm-started from omegas[b][l - 1]); infos[b][l] its dict.
+    """
+    import numpy as np
+    lib = load()
+    B = len(Xs)
+    if B < 1:
+        raise ValueError("need at least one problem")
+    lam = np.asarray(lambdas, dtype=np.float64)
+    if lam.ndim == 1:
+        lam = np.broadcast_to(lam, (B, lam.shape[0]))
+    if lam.ndim != 2 or lam.shape[0] != B:
+        raise ValueError("lambdas must be B x L")
+    lam = np.ascontiguousarray(lam)
+    L = lam.shape[1]
+    dt = _dtype_code(Xs[0])
+    ps, ns = [], []
+    for b, X in enumerate(Xs):
+        _check_dev(X, f"Xs[{b}]")
+        if X.dtype != Xs[0].dtype or X.device != Xs[0].device:
+            raise ValueError("all problems must share dtype and device")
+        if kind == "S":
+            if X.dim() != 2 or X.shape[0] != X.shape[1]:
+                raise ValueError("S must be square")
+            ps.append(X.shape[0])
+            ns.append(0)
+        elif kind == "Y":
+            if X.dim() != 2:
+                raise ValueError("Y must be a matrix")
+            ns.append(X.shape[0])
+            ps.append(X.shape[1])
+        else:
+            raise ValueError("kind must be 'S' or 'Y'")
+    if outs is None:
+        outs = [[torch.empty((ps[b], ps[b]), dtype=Xs[0].dtype, device=Xs[0].device)
+                 for _ in range(L)] for b in range(B)]
+    for b in range(B):
+        if len(outs[b]) != L:
+            raise ValueError("outs must be B x L")
+        for l in range(L):
+            o = outs[b][l]
+            _check_dev(o, "outs")
+            if o.dtype != Xs[0].dtype or tuple(o.shape) != (ps[b], ps[b]):
+                raise ValueError("each output must be p_b x p_b with the inputs' dtype")
+    vp = ctypes.c_void_p
+    xa = (vp * B)(*[X.data_ptr() for X in Xs])
+    na = (ctypes.c_int64 * B)(*ns)
+    pa = (ctypes.c_int64 * B)(*ps)
+    la = (ctypes.c_double * (B * L))(*lam.ravel().tolist())
+    oa = (vp * (B * L))(*[outs[b][l].data_ptr() for b in range(B) for l in range(L)])
+    infos = (ConcordInfo * (B * L))()
+    opts = ConcordBatchOptions(workgroups, block_threads, pending_depth, 0, None)
+    pw = None
+    if problem_workgroups is not None:
+        if len(problem_workgroups) != B:
+            raise ValueError("problem_workgroups needs one count per problem")
+        pw = (ctypes.c_int32 * B)(*[int(x) for x in problem_workgroups])
+        opts.problem_workgroups = ctypes.cast(pw, ctypes.POINTER(ctypes.c_int32))
+    with torch.cuda.device(Xs[0].device):
+        code = lib.concord_fit_batched_ex(B, INPUT_S if kind == "S" else INPUT_Y, xa, na, pa, L,
+                                          la, float(tol), int(maxit), dt, oa, infos,
+                                          _stream_handle(stream), ctypes.byref(opts))
+    di = [[infos[b * L + l].as_dict() for l in range(L)] for b in range(B)]
+    if check:
+        _raise(code, "concord_fit_batched")
+    return outs, di, code
 
 
 def gram(Y: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:

@@ -122,12 +122,13 @@ int choose_shape(int p, const concord_options *o, Shape *sh)
     sh->nc_max = ncm;
     const size_t cap = (size_t)max_shared_per_block();
     auto lds_need = [&](int d, bool w) {
-        size_t b = sizeof(T) * ((size_t)sh->nr_max * d + 16) +
-                   sizeof(int) * ((size_t)sh->nr_max * d + 2 * (size_t)sh->nr_max + 4) +
-                   sizeof(unsigned) * 16;
-        if (w)
-            b += sizeof(T) * (size_t)sh->nr_max * sh->nc_max;
-        return b;
+        SweepParams<T> probe;
+        memset(&probe, 0, sizeof(probe));
+        probe.nr_max = sh->nr_max;
+        probe.nc_max = sh->nc_max;
+        probe.depth = d;
+        probe.w_lds = w ? 1 : 0;
+        return sweep_lds_bytes<T>(probe);
     };
     // W in LDS: updates are cheap, apply them at once (depth 2).  W in HBM:
     // hold up to 8 pending updates per row.
@@ -269,6 +270,8 @@ int fit_impl(concord_input kind, const void *X, int64_t n64, int64_t p64, double
     CK_HIP(hipEventRecord(ev[5], stream));
     CK_HIP(launch_finalize<T>(omp, omdp, sh.Gr, sh.Gc, sh.nr_max, W, p, (T)lambda, (T *)omega, acc,
                               nnz, out + 4, stream));
+    if (opts && opts->w_out)
+        CK_HIP(hipMemcpyAsync(opts->w_out, W, sizeof(T) * pp, hipMemcpyDeviceToDevice, stream));
     CK_HIP(hipEventRecord(ev[1], stream));
 
     // One readback: status words, summary accumulators and the per-sweep
@@ -349,6 +352,362 @@ int fit_impl(concord_input kind, const void *X, int64_t n64, int64_t p64, double
     return status;
 }
 
+// ---------------------------------------------------------------- batched
+
+// Status of a batch: the first negative code met, else NOT_CONVERGED if any
+// solve stopped at maxit, else OK.
+int merge_status(int acc, int s)
+{
+    if (acc < 0)
+        return acc;
+    if (s < 0)
+        return s;
+    return (s == CONCORD_NOT_CONVERGED || acc == CONCORD_NOT_CONVERGED) ? CONCORD_NOT_CONVERGED
+                                                                         : CONCORD_OK;
+}
+
+// Workgroups for each problem of a batch sharing `total` workgroups.  Each
+// problem needs ceil(p / (2 * threads)) workgroups (two rows per thread at
+// most) and keeps at least 8 rows per workgroup.  The rest are dealt one at a
+// time to the problem with the largest work per workgroup, work ~ p^1.55:
+// along a descending lambda path with n ~ p / 2 the bytes a solve moves grow
+// like that (smaller problems need more sweeps), which is what the measured
+// per-problem device times of such batches follow.  Returns false when the
+// minimum does not fit.
+bool plan_workgroups(const std::vector<int> &ps, int total, int threads, std::vector<int> *G)
+{
+    const int B = (int)ps.size();
+    G->assign(B, 1);
+    long long used = 0;
+    std::vector<double> w(B);
+    for (int b = 0; b < B; ++b) {
+        (*G)[b] = std::max(1, (ps[b] + 2 * threads - 1) / (2 * threads));
+        used += (*G)[b];
+        w[b] = pow((double)ps[b], 1.55);
+    }
+    if (used > total)
+        return false;
+    for (long long left = total - used; left > 0; --left) {
+        int best = -1;
+        double bc = -1.0;
+        for (int b = 0; b < B; ++b) {
+            if ((*G)[b] * 8 > ps[b])  // keep >= 8 rows per workgroup
+                continue;
+            const double c = w[b] / (*G)[b];
+            if (c > bc) {
+                bc = c;
+                best = b;
+            }
+        }
+        if (best < 0)
+            break;
+        ++(*G)[best];
+    }
+    return true;
+}
+
+template <typename T>
+int batched_chunk(int B0, int B1, concord_input kind, const void *const *X, const int64_t *n,
+                  const int64_t *pv, int L, const double *lambdas, double tol, int maxit,
+                  void *const *omega, concord_info *info, hipStream_t stream,
+                  const std::vector<int> &Gb, int threads, int depth)
+{
+    const int NB = B1 - B0;
+    hipEvent_t ev[4] = {};
+    struct EvGuard {
+        hipEvent_t *e;
+        ~EvGuard()
+        {
+            for (int k = 0; k < 4; ++k)
+                if (e[k])
+                    (void)hipEventDestroy(e[k]);
+        }
+    } evg{ev};
+    for (int k = 0; k < 4; ++k)
+        CK_HIP(hipEventCreate(&ev[k]));
+
+    // Per-problem shapes and workspace offsets.
+    struct Prob {
+        int p, G, nr, m;
+        size_t oS, oW, oOmp, oOmdp, oSd, oPc, oPd, oFlags, oRed, oOut, oRec, oLam, oOm;
+    };
+    std::vector<Prob> pr(NB);
+    Carver cv;
+    int Gtot = 0;
+    size_t lds = 0;
+    for (int q = 0; q < NB; ++q) {
+        const int b = B0 + q;
+        Prob &P = pr[q];
+        P.p = (int)pv[b];
+        P.G = Gb[b];
+        P.nr = (P.p + P.G - 1) / P.G;
+        P.m = Circle::make(P.p).m;
+        const size_t pp = (size_t)P.p * P.p;
+        P.oS = (kind == CONCORD_INPUT_Y) ? cv.take<T>(pp) : 0;
+        P.oW = cv.take<T>(pp);
+        P.oOmp = cv.take<T>((size_t)P.G * P.m * P.nr);
+        P.oOmdp = cv.take<T>((size_t)P.G * P.nr);
+        P.oSd = cv.take<T>(P.p);
+        const size_t PS = (size_t)P.G * P.nr;
+        P.oPc = cv.take<T>(2 * (size_t)P.m * PS);
+        P.oPd = cv.take<T>(2 * PS);
+        P.oFlags = cv.take<unsigned>(P.G);
+        P.oRed = cv.take<unsigned long long>(4 * (size_t)L * maxit);
+        P.oOut = cv.take<int>(kOutWords);
+        P.oRec = cv.take<PathRec>(L);
+        P.oLam = cv.take<double>(L);
+        P.oOm = cv.take<T *>(L);
+        SweepParams<T> probe;
+        memset(&probe, 0, sizeof(probe));
+        probe.nr_max = P.nr;
+        probe.nc_max = P.p;
+        probe.depth = depth;
+        lds = std::max(lds, sweep_lds_bytes<T>(probe));
+        Gtot += P.G;
+    }
+    if (lds > (size_t)max_shared_per_block())
+        return CONCORD_ELAUNCH;
+    const size_t oDesc = cv.take<SweepParams<T>>(NB);
+    const size_t oMap = cv.take<int>(Gtot);
+    Workspace ws;
+    ws.stream = stream;
+    ws.bytes = cv.off;
+    {
+        hipError_t e = hipMallocAsync(&ws.base, ws.bytes, stream);
+        if (e != hipSuccess) {
+            ws.base = nullptr;
+            return map_hip(e);
+        }
+    }
+    char *base = (char *)ws.base;
+
+    // Descriptors, the workgroup -> problem map, lambda paths and output
+    // pointer tables (host copies live until the final synchronisation).
+    std::vector<SweepParams<T>> desc(NB);
+    std::vector<int> wmap(Gtot);
+    std::vector<double> hl((size_t)NB * L);
+    std::vector<T *> hom((size_t)NB * L);
+    CK_HIP(hipEventRecord(ev[0], stream));
+    int g0 = 0;
+    for (int q = 0; q < NB; ++q) {
+        const int b = B0 + q;
+        const Prob &P = pr[q];
+        T *S = (kind == CONCORD_INPUT_Y) ? (T *)(base + P.oS) : (T *)X[b];
+        T *W = (T *)(base + P.oW);
+        T *omp = (T *)(base + P.oOmp), *omdp = (T *)(base + P.oOmdp), *sd = (T *)(base + P.oSd);
+        T *pc = (T *)(base + P.oPc), *pd = (T *)(base + P.oPd);
+        int *out = (int *)(base + P.oOut);
+        CK_HIP(launch_clear((unsigned *)(base + P.oFlags), P.G,
+                            (unsigned long long *)(base + P.oRed), 4 * L * maxit, out, kOutWords,
+                            (double *)(base + P.oRec), (int)(sizeof(PathRec) / 8) * L, stream));
+        static_assert(sizeof(PathRec) % 8 == 0, "PathRec is cleared as 8-byte words");
+        if (kind == CONCORD_INPUT_Y)
+            CK_HIP(launch_gram<T>((const T *)X[b], (int)n[b], P.p, S, stream));
+        CK_HIP(launch_check_copy<T>(S, P.p, W, true, sd, out + 4, stream));
+        CK_HIP(launch_init_omega<T>(nullptr, P.p, P.G, 1, P.nr, omp, omdp, out + 4, stream));
+        CK_HIP(launch_init_publish<T>(W, P.p, P.G, P.nr, pc, pd, stream));
+        for (int l = 0; l < L; ++l) {
+            hl[(size_t)q * L + l] = lambdas[(size_t)b * L + l];
+            hom[(size_t)q * L + l] = (T *)omega[(size_t)b * L + l];
+        }
+        SweepParams<T> &D = desc[q];
+        memset(&D, 0, sizeof(D));
+        D.S = S;
+        D.sd = sd;
+        D.W = W;
+        D.omp = omp;
+        D.omdp = omdp;
+        D.pc = pc;
+        D.pd = pd;
+        D.flags = (unsigned *)(base + P.oFlags);
+        D.red = (unsigned long long *)(base + P.oRed);
+        D.out = out;
+        D.p = P.p;
+        D.Gr = P.G;
+        D.Gc = 1;
+        D.maxit = maxit;
+        D.w_lds = 0;
+        D.nr_max = P.nr;
+        D.nc_max = P.p;
+        D.depth = depth;
+        D.rpt = 2;
+        D.lam = (T)hl[(size_t)q * L];
+        D.tol = (T)tol;
+        D.tol_coef = (sizeof(T) == 4) ? T(16.0 * 1.1920928955078125e-07) : T(0);
+        D.spin_limit = kSpinLimit;
+        D.L = L;
+        D.lams = (const double *)(base + P.oLam);
+        D.omega_out = (T *const *)(base + P.oOm);
+        D.rec = (PathRec *)(base + P.oRec);
+        D.g0 = g0;
+        for (int g = 0; g < P.G; ++g)
+            wmap[g0 + g] = q;
+        g0 += P.G;
+        CK_HIP(hipMemcpyAsync(base + P.oLam, &hl[(size_t)q * L], sizeof(double) * L,
+                              hipMemcpyHostToDevice, stream));
+        CK_HIP(hipMemcpyAsync(base + P.oOm, &hom[(size_t)q * L], sizeof(T *) * L,
+                              hipMemcpyHostToDevice, stream));
+    }
+    CK_HIP(hipMemcpyAsync(base + oDesc, desc.data(), sizeof(SweepParams<T>) * NB,
+                          hipMemcpyHostToDevice, stream));
+    CK_HIP(hipMemcpyAsync(base + oMap, wmap.data(), sizeof(int) * Gtot, hipMemcpyHostToDevice,
+                          stream));
+    CK_HIP(hipEventRecord(ev[1], stream));
+    CK_HIP(launch_sweep_batched<T>((const SweepParams<T> *)(base + oDesc),
+                                   (const int *)(base + oMap), Gtot, lds, threads, stream));
+    CK_HIP(hipEventRecord(ev[2], stream));
+
+    // Readback: status words, per-sweep reductions and per-lambda records.
+    std::vector<int> hout((size_t)NB * kOutWords);
+    std::vector<unsigned long long> hred((size_t)NB * 4 * L * maxit);
+    std::vector<PathRec> hrec((size_t)NB * L);
+    for (int q = 0; q < NB; ++q) {
+        const Prob &P = pr[q];
+        CK_HIP(hipMemcpyAsync(&hout[(size_t)q * kOutWords], base + P.oOut, sizeof(int) * kOutWords,
+                              hipMemcpyDeviceToHost, stream));
+        CK_HIP(hipMemcpyAsync(&hred[(size_t)q * 4 * L * maxit], base + P.oRed,
+                              sizeof(unsigned long long) * 4 * L * maxit, hipMemcpyDeviceToHost,
+                              stream));
+        CK_HIP(hipMemcpyAsync(&hrec[(size_t)q * L], base + P.oRec, sizeof(PathRec) * L,
+                              hipMemcpyDeviceToHost, stream));
+    }
+    CK_HIP(hipEventRecord(ev[3], stream));
+    CK_HIP(hipStreamSynchronize(stream));
+    float ms = 0.f, ms_setup = 0.f, ms_sweep = 0.f;
+    (void)hipEventElapsedTime(&ms, ev[0], ev[3]);
+    (void)hipEventElapsedTime(&ms_setup, ev[0], ev[1]);
+    (void)hipEventElapsedTime(&ms_sweep, ev[1], ev[2]);
+
+    auto bits_to = [](unsigned long long u) -> double {
+        if (sizeof(T) == 8) {
+            double d;
+            memcpy(&d, &u, 8);
+            return d;
+        }
+        uint32_t w = (uint32_t)u;
+        float f;
+        memcpy(&f, &w, 4);
+        return (double)f;
+    };
+    int worst = CONCORD_OK;
+    for (int q = 0; q < NB; ++q) {
+        const int b = B0 + q;
+        const int *ho = &hout[(size_t)q * kOutWords];
+        const unsigned long long *hr = &hred[(size_t)q * 4 * L * maxit];
+        int pstat = CONCORD_OK;
+        if (ho[4] & kErrNotPD)
+            pstat = CONCORD_ENOTPD;
+        else if (ho[4] & kErrNonFinite)
+            pstat = CONCORD_ENONFINITE;
+        else if (ho[2] || ho[3])
+            pstat = CONCORD_EDEVICE;
+        int t0 = 0;
+        for (int l = 0; l < L; ++l) {
+            const PathRec &rc = hrec[(size_t)q * L + l];
+            int status = pstat;
+            int t1 = rc.t_end;
+            if (status == CONCORD_OK && t1 <= t0)
+                status = CONCORD_EDEVICE;  // the path stopped before this lambda
+            if (status == CONCORD_OK)
+                status = rc.converged ? CONCORD_OK : CONCORD_NOT_CONVERGED;
+            if (t1 < t0)
+                t1 = t0;
+            concord_info *I = info ? &info[(size_t)b * L + l] : nullptr;
+            if (I) {
+                memset(I, 0, sizeof(*I));
+                I->sweeps = t1 - t0;
+                I->status = status;
+                if (t1 > t0) {
+                    I->delta = bits_to(hr[4 * (size_t)(t1 - 1)]);
+                    const double gmax = bits_to(hr[4 * (size_t)(t1 - 1) + 1]);
+                    I->tol_eff = std::max(tol, (sizeof(T) == 4 ? 16.0 * 1.1920928955078125e-07 : 0.0) * gmax);
+                } else {
+                    I->tol_eff = tol;
+                }
+                int64_t mv = 0, mvd = 0;
+                for (int t = t0; t < t1; ++t) {
+                    mv += (int64_t)hr[4 * (size_t)t + 2];
+                    mvd += (int64_t)hr[4 * (size_t)t + 3];
+                }
+                I->nnz_upper = (int64_t)rc.nnz_upper;
+                I->objective = rc.objective;
+                I->elapsed_ms = ms;
+                I->gram_ms = ms_setup;
+                // this lambda's own device time (100 MHz clock); the launch's
+                // sweep time when the path stopped before it
+                I->sweep_ms = (rc.clock_end > rc.clock_start)
+                                  ? (double)(rc.clock_end - rc.clock_start) * 1e-5
+                                  : (double)ms_sweep;
+                I->moved_pairs = mv;
+                I->moved_diag = mvd;
+                I->row_groups = pr[q].G;
+                I->col_slices = 1;
+                I->w_in_lds = 0;
+                I->block_threads = threads;
+                I->pending_depth = depth;
+            }
+            worst = merge_status(worst, status);
+            t0 = t1;
+        }
+    }
+    return worst;
+}
+
+template <typename T>
+int batched_impl(int B, concord_input kind, const void *const *X, const int64_t *n,
+                 const int64_t *pv, int L, const double *lambdas, double tol, int maxit,
+                 void *const *omega, concord_info *info, hipStream_t stream,
+                 const concord_batch_options *o)
+{
+    const int cus = std::max(1, cu_count());
+    int total = (o && o->workgroups > 0) ? o->workgroups : cus;
+    int threads = (o && o->block_threads > 0) ? o->block_threads : 512;
+    int depth = (o && o->pending_depth > 0) ? o->pending_depth : 8;
+    if (o && (o->workgroups < 0 || o->block_threads < 0 || o->pending_depth < 0))
+        return CONCORD_EINVAL;
+    if (total > cus || threads % 64 != 0 || threads > 512 || depth < 2 || depth > 8)
+        return CONCORD_EINVAL;
+    // Problems go in order into launches of at most `total` workgroups.
+    std::vector<int> minG(B);
+    for (int b = 0; b < B; ++b)
+        minG[b] = std::max(1, (int)((pv[b] + 2 * threads - 1) / (2 * threads)));
+    const int32_t *fixed = o ? o->problem_workgroups : nullptr;
+    if (fixed) {
+        long long sum = 0;
+        for (int b = 0; b < B; ++b) {
+            if (fixed[b] < minG[b] || fixed[b] > pv[b])
+                return CONCORD_EINVAL;
+            sum += fixed[b];
+        }
+        if (sum > total)
+            return CONCORD_EINVAL;
+    }
+    std::vector<int> Gb(B, 1);
+    int worst = CONCORD_OK;
+    for (int b0 = 0; b0 < B;) {
+        int b1 = b0;
+        long long used = 0;
+        while (b1 < B && used + minG[b1] <= total)
+            used += minG[b1++];
+        if (b1 == b0)
+            return CONCORD_ELAUNCH;
+        std::vector<int> ps(pv + b0, pv + b1), G;
+        if (fixed)
+            G.assign(fixed + b0, fixed + b1);
+        else if (!plan_workgroups(ps, total, threads, &G))
+            return CONCORD_ELAUNCH;
+        for (int b = b0; b < b1; ++b)
+            Gb[b] = G[b - b0];
+        const int rc = batched_chunk<T>(b0, b1, kind, X, n, pv, L, lambdas, tol, maxit, omega,
+                                        info, stream, Gb, threads, depth);
+        worst = merge_status(worst, rc);
+        if (rc == CONCORD_ENOMEM || rc == CONCORD_EDEVICE || rc == CONCORD_ELAUNCH)
+            return rc;
+        b0 = b1;
+    }
+    return worst;
+}
+
 int validate(concord_input kind, const void *X, int64_t n, int64_t p, double lambda, double tol,
              int32_t maxit, concord_dtype dt, void *omega)
 {
@@ -401,6 +760,40 @@ extern "C" int concord_fit(concord_input kind, const void *X, int64_t n, int64_t
 {
     return concord_fit_ex(kind, X, n, p, lambda, tol, maxit, dt, omega0, omega, info, stream,
                           nullptr);
+}
+
+extern "C" int concord_fit_batched_ex(int32_t B, concord_input kind, const void *const *X,
+                                      const int64_t *n, const int64_t *p, int32_t L,
+                                      const double *lambdas, double tol, int32_t maxit,
+                                      concord_dtype dt, void *const *omega, concord_info *info,
+                                      void *stream, const concord_batch_options *opts)
+{
+    if (B < 1 || L < 1 || !X || !p || !lambdas || !omega || (kind == CONCORD_INPUT_Y && !n) ||
+        (long long)L * maxit > (1ll << 24))
+        return CONCORD_EINVAL;
+    for (int b = 0; b < B; ++b) {
+        for (int l = 0; l < L; ++l) {
+            int rc = validate(kind, X[b], n ? n[b] : 1, p[b], lambdas[(size_t)b * L + l], tol,
+                              maxit, dt, omega[(size_t)b * L + l]);
+            if (rc)
+                return rc;
+        }
+    }
+    hipStream_t st = (hipStream_t)stream;
+    if (dt == CONCORD_F64)
+        return batched_impl<double>(B, kind, X, n, p, L, lambdas, tol, maxit, omega, info, st,
+                                    opts);
+    return batched_impl<float>(B, kind, X, n, p, L, lambdas, tol, maxit, omega, info, st, opts);
+}
+
+extern "C" int concord_fit_batched(int32_t B, concord_input kind, const void *const *X,
+                                   const int64_t *n, const int64_t *p, int32_t L,
+                                   const double *lambdas, double tol, int32_t maxit,
+                                   concord_dtype dt, void *const *omega, concord_info *info,
+                                   void *stream)
+{
+    return concord_fit_batched_ex(B, kind, X, n, p, L, lambdas, tol, maxit, dt, omega, info,
+                                  stream, nullptr);
 }
 
 extern "C" int concord_gram(const void *Y, int64_t n, int64_t p, concord_dtype dt, void *S,

@@ -51,14 +51,13 @@ constexpr int kMaxDepth = 8;  // longest pending list (registers hold one S valu
 // workgroup polls all flags.  Bounded: after spin_limit polls (or when any
 // workgroup has raised the abort word) it gives up and reports failure.
 template <typename T>
-__device__ bool sweep_barrier(const SweepParams<T> &P, unsigned epoch, int *s_fail)
+__device__ bool sweep_barrier(const SweepParams<T> &P, unsigned epoch, int *s_fail, int g, int G)
 {
     wait_stores();
     __syncthreads();
-    const int G = gridDim.x;
     if (G > 1) {
         if (threadIdx.x == 0)
-            st_dev(&P.flags[blockIdx.x], epoch);
+            st_dev(&P.flags[g], epoch);
         if (threadIdx.x < 64) {
             long long spins = 0;
             for (;;) {
@@ -125,46 +124,52 @@ __device__ __forceinline__ T as_value(typename Sentinel<T>::U u)
 
 // Rewrites the segments of the listed rows with their pending updates:
 // W_ic <- fma(d_e, S_{src_e, c}, ...) in list order, for c in the slice.
-// Work is cut into (row, 128-column chunk) units dealt out to the waves; each
-// lane handles two columns so that 2 (n + 1) loads are in flight per lane.
-template <typename T, bool WLDS>
+// Work is cut into (row, 64 * CPL column chunk) units dealt out to the waves;
+// each lane handles CPL columns 64 apart (every load is one coalesced row
+// segment), so CPL * (n + 1) loads are in flight per lane.
+template <typename T, bool WLDS, int CPL>
 __device__ void flush_rows(const int *rows, int nrows, const int *pj, const T *pdl,
                            const int *np, int D, int a, int Gr, int p, int c0, int nc,
                            const T *__restrict__ S, T *__restrict__ Wg, T *wblk)
 {
+    constexpr int CW = 64 * CPL;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    const int chunks = (nc + 127) >> 7;
+    const int chunks = (nc + CW - 1) / CW;
     const int units = nrows * chunks;
     for (int u = wv; u < units; u += nw) {
         const int fr = u / chunks, ch = u - fr * chunks;
         const int k = rows[fr];
         const int i = a + k * Gr;
         const int n = np[k];
-        const int cA = ch * 128 + lane, cB = cA + 64;
-        const bool okA = cA < nc, okB = cB < nc;
-        T sa[kMaxDepth], sb[kMaxDepth];
+        const int cl = ch * CW + lane;
+        T sv[kMaxDepth][CPL];
 #pragma unroll
         for (int e = 0; e < kMaxDepth; ++e) {
             if (e < n) {
                 const T *row = S + (size_t)pj[k * D + e] * p + c0;
-                sa[e] = okA ? row[cA] : T(0);
-                sb[e] = okB ? row[cB] : T(0);
+#pragma unroll
+                for (int q = 0; q < CPL; ++q)
+                    sv[e][q] = (cl + 64 * q < nc) ? row[cl + 64 * q] : T(0);
             }
         }
-        T *wa = WLDS ? &wblk[(size_t)k * nc] : &Wg[(size_t)i * p + c0];
-        T va = okA ? wa[cA] : T(0), vb = okB ? wa[cB] : T(0);
+        T *wr = WLDS ? &wblk[(size_t)k * nc] : &Wg[(size_t)i * p + c0];
+        T v[CPL];
+#pragma unroll
+        for (int q = 0; q < CPL; ++q)
+            v[q] = (cl + 64 * q < nc) ? wr[cl + 64 * q] : T(0);
 #pragma unroll
         for (int e = 0; e < kMaxDepth; ++e) {
             if (e < n) {
                 const T d = pdl[k * D + e];
-                va = fma(d, sa[e], va);
-                vb = fma(d, sb[e], vb);
+#pragma unroll
+                for (int q = 0; q < CPL; ++q)
+                    v[q] = fma(d, sv[e][q], v[q]);
             }
         }
-        if (okA)
-            wa[cA] = va;
-        if (okB)
-            wa[cB] = vb;
+#pragma unroll
+        for (int q = 0; q < CPL; ++q)
+            if (cl + 64 * q < nc)
+                wr[cl + 64 * q] = v[q];
     }
 }
 
@@ -213,16 +218,98 @@ __device__ __forceinline__ void load_next(RowNext<T> &x, const Circle &C, int r1
 
 }  // namespace
 
-template <typename T, bool WLDS, int RPT>
-__global__ void __launch_bounds__(512) pcd_sweep_kernel(SweepParams<T> P)
+// End of one lambda of a path: apply every pending row update to the stored
+// W block, then write this workgroup's block of the dense Omega (rows
+// i = a (mod Gr), columns of slice b) and add its share of |E-hat| and of the
+// objective F(Omega) = -sum log omega_ii + 1/2 sum_ij omega_ij W_ij
+// + lam sum_{i<j} |omega_ij| to the lambda's record.
+template <typename T, bool WLDS, int RPT, int CPL>
+__device__ void end_of_lambda(const SweepParams<T> &P, int l, T lam, const Circle &C, int a,
+                              int Gr, int nr, int NR, int D, int c0, int nc, int *np, int *flist,
+                              int *ncount, const int *pj, const T *pdl, bool (&flushed)[RPT],
+                              T *wblk, const T *omp, const T *omdp, double *dred,
+                              unsigned long long *nred)
+{
+    const int tid = threadIdx.x, nthr = blockDim.x, p = P.p;
+    __syncthreads();
+    if (tid == 0)
+        *ncount = 0;
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) {
+        const int k = tid + u * nthr;
+        if (k < nr) {
+            if (flushed[u]) {
+                np[k] = 0;
+                flushed[u] = false;
+            }
+            if (np[k] > 0)
+                flist[atomicAdd(ncount, 1)] = k;
+        }
+    }
+    __syncthreads();
+    flush_rows<T, WLDS, CPL>(flist, *ncount, pj, pdl, np, D, a, Gr, p, c0, nc, P.S, P.W, wblk);
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) {
+        const int k = tid + u * nthr;
+        if (k < nr)
+            np[k] = 0;
+    }
+    T *om = P.omega_out[l];
+    double part = 0.0;
+    unsigned long long cnt = 0;
+    for (long e = tid; e < (long)nr * nc; e += nthr) {
+        const int k = (int)(e / nc), c = (int)(e - (long)k * nc);
+        const int i = a + k * Gr, j = c0 + c;
+        const T wij = WLDS ? wblk[(size_t)k * nc + c] : P.W[(size_t)i * p + j];
+        T w;
+        if (i == j) {
+            w = omdp[k];
+            part -= log((double)w);
+        } else {
+            w = omp[(size_t)C.colour(i, j) * NR + k];
+            if (i < j) {
+                part += (double)lam * fabs((double)w);
+                cnt += (w != T(0)) ? 1ull : 0ull;
+            }
+        }
+        part += 0.5 * (double)w * (double)wij;
+        om[(size_t)i * p + j] = w;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        part += __shfl_xor(part, off, 64);
+        cnt += __shfl_xor(cnt, off, 64);
+    }
+    const int wv = tid >> 6, nw = nthr >> 6;
+    if ((tid & 63) == 0) {
+        dred[wv] = part;
+        nred[wv] = cnt;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double sp = 0.0;
+        unsigned long long sc = 0;
+        for (int w2 = 0; w2 < nw; ++w2) {
+            sp += dred[w2];
+            sc += nred[w2];
+        }
+        atomicAdd(&P.rec[l].objective, sp);
+        atomicAdd(&P.rec[l].nnz_upper, sc);
+    }
+    __syncthreads();
+}
+
+// One solve (a whole lambda path) by workgroup g of the G workgroups that
+// share the problem described by P.  CPL: columns per lane in row rewrites.
+template <typename T, bool WLDS, int RPT, int CPL>
+__device__ void pcd_solve(const SweepParams<T> &P, int g, int G, unsigned char *smem_raw)
 {
     using U = typename Sentinel<T>::U;
     constexpr U SENT = Sentinel<T>::bits;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
     const Circle C = Circle::make(P.p);
     const int p = P.p, m = C.m;
     const int tid = threadIdx.x, nthr = blockDim.x;
-    const int g = blockIdx.x, G = gridDim.x;
     const int a = g / P.Gc, b = g % P.Gc;
     const int Gr = P.Gr;
     const int nr = (a < p) ? (p - a + Gr - 1) / Gr : 0;
@@ -238,9 +325,11 @@ __global__ void __launch_bounds__(512) pcd_sweep_kernel(SweepParams<T> P)
     int *pj = reinterpret_cast<int *>(wblk + (WLDS ? (size_t)NR * P.nc_max : 0));  // NR x D sources
     int *np = pj + (size_t)NR * D;              // pending count per row
     int *flist = np + NR;                       // rows to rewrite this step
-    int *nflush = flist + NR;                   // [3] counters, by step mod 3
-    int *s_fail = nflush + 3;
+    int *nflush = flist + NR;                   // [3] counters, by step mod 3; [3] spare
+    int *s_fail = nflush + 4;
     unsigned *ured = reinterpret_cast<unsigned *>(s_fail + 1);  // 16 wave partials
+    double *dred = reinterpret_cast<double *>(((uintptr_t)(ured + 16) + 7) & ~(uintptr_t)7);
+    unsigned long long *nred = reinterpret_cast<unsigned long long *>(dred + 16);
 
     const T *__restrict__ S = P.S;
     const T *__restrict__ sd = P.sd;
@@ -254,6 +343,7 @@ __global__ void __launch_bounds__(512) pcd_sweep_kernel(SweepParams<T> P)
         nflush[0] = 0;
         nflush[1] = 0;
         nflush[2] = 0;
+        nflush[3] = 0;
         *s_fail = 0;
     }
     if (WLDS) {
@@ -282,6 +372,15 @@ __global__ void __launch_bounds__(512) pcd_sweep_kernel(SweepParams<T> P)
     // A set-up kernel that found bad input leaves its bits in out[4]; then
     // every workgroup skips the sweeps (the same word is read by all).
     const bool run = ld_dev(&P.out[4]) == 0;
+
+    // Lambda path: lambda l runs until its own convergence test passes or
+    // maxit sweeps, then the next starts from where it stopped (warm start:
+    // Omega, W and the published entries carry over unchanged).
+    const int L = P.L > 0 ? P.L : 1;
+    int lidx = 0, tl = 0;
+    T lam = P.lams ? (T)P.lams[0] : P.lam;
+    if (P.rec && g == 0 && tid == 0)
+        P.rec[0].clock_start = __builtin_amdgcn_s_memrealtime();
 
     while (run) {
         const int cur = t & 1, nxt = cur ^ 1;
@@ -395,7 +494,7 @@ __global__ void __launch_bounds__(512) pcd_sweep_kernel(SweepParams<T> P)
                     const int lo = j < i ? j : i, hi = j < i ? i : j;
                     const T sden = sd[lo] + sd[hi];
                     const T bnum = fma(-sden, x.w, as_value<T>(blo) + as_value<T>(bhi));
-                    const T wn = soft_threshold(-bnum, P.lam) / sden;
+                    const T wn = soft_threshold(-bnum, lam) / sden;
                     del = wn - x.w;
                     if (del != T(0))
                         omp[(size_t)r * NR + k] = wn;
@@ -478,7 +577,7 @@ __global__ void __launch_bounds__(512) pcd_sweep_kernel(SweepParams<T> P)
                 }
                 const int nf = nflush[s3];
                 if (nf > 0) {
-                    flush_rows<T, WLDS>(flist, nf, pj, pdl, np, D, a, Gr, p, c0, nc, S, Wg, wblk);
+                    flush_rows<T, WLDS, CPL>(flist, nf, pj, pdl, np, D, a, Gr, p, c0, nc, S, Wg, wblk);
                     __syncthreads();
                 }
             }
@@ -509,27 +608,42 @@ __global__ void __launch_bounds__(512) pcd_sweep_kernel(SweepParams<T> P)
         gloc = T(0);
         moved = 0;
         moved_d = 0;
-        if (!sweep_barrier(P, (unsigned)(t + 1), s_fail)) {
+        if (!sweep_barrier(P, (unsigned)(t + 1), s_fail, g, G)) {
             failed = 1;
             break;
         }
         const T delta = from_ord(ld_dev(&P.red[4 * (size_t)t]), T(0));
         const T gmax = from_ord(ld_dev(&P.red[4 * (size_t)t + 1]), T(0));
         ++t;
+        ++tl;
         T tol_eff = P.tol_coef * gmax;
         tol_eff = tol_eff > P.tol ? tol_eff : P.tol;
-        if (delta < tol_eff) {
-            converged = 1;
-            break;
+        const bool conv = delta < tol_eff;
+        if (conv || tl >= P.maxit) {
+            converged = conv ? 1 : 0;
+            if (P.omega_out)
+                end_of_lambda<T, WLDS, RPT, CPL>(P, lidx, lam, C, a, Gr, nr, NR, D, c0, nc, np, flist,
+                                            &nflush[3], pj, pdl, flushed, wblk, omp, omdp, dred,
+                                            nred);
+            if (P.rec && g == 0 && tid == 0) {
+                const unsigned long long now = __builtin_amdgcn_s_memrealtime();
+                P.rec[lidx].t_end = t;
+                P.rec[lidx].converged = converged;
+                P.rec[lidx].clock_end = now;
+                if (lidx + 1 < L)
+                    P.rec[lidx + 1].clock_start = now;
+            }
+            if (++lidx >= L)
+                break;
+            lam = (T)P.lams[lidx];
+            tl = 0;
         }
-        if (t >= P.maxit)
-            break;
     }
 
     // Apply every pending update so that the stored W is Omega S again.
     __syncthreads();
     if (tid == 0)
-        nflush[0] = 0;
+        nflush[3] = 0;
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < RPT; ++u) {
@@ -538,11 +652,11 @@ __global__ void __launch_bounds__(512) pcd_sweep_kernel(SweepParams<T> P)
             if (flushed[u])
                 np[k] = 0;
             if (np[k] > 0)
-                flist[atomicAdd(&nflush[0], 1)] = k;
+                flist[atomicAdd(&nflush[3], 1)] = k;
         }
     }
     __syncthreads();
-    flush_rows<T, WLDS>(flist, nflush[0], pj, pdl, np, D, a, Gr, p, c0, nc, S, Wg, wblk);
+    flush_rows<T, WLDS, CPL>(flist, nflush[3], pj, pdl, np, D, a, Gr, p, c0, nc, S, Wg, wblk);
     __syncthreads();
     if (WLDS) {
         for (long e = tid; e < (long)nr * nc; e += nthr) {
@@ -563,9 +677,34 @@ size_t sweep_lds_bytes(const SweepParams<T> &P)
     size_t bytes = sizeof(T) * ((size_t)P.nr_max * P.depth + 16);
     if (P.w_lds)
         bytes += sizeof(T) * (size_t)P.nr_max * P.nc_max;
-    bytes += sizeof(int) * ((size_t)P.nr_max * P.depth + 2 * (size_t)P.nr_max + 4);
+    bytes += sizeof(int) * ((size_t)P.nr_max * P.depth + 2 * (size_t)P.nr_max + 5);
     bytes += sizeof(unsigned) * 16;
+    bytes += 8 + sizeof(double) * 16 + sizeof(unsigned long long) * 16;  // path summaries
     return bytes;
+}
+
+template <typename T, bool WLDS, int RPT>
+__global__ void __launch_bounds__(512) pcd_sweep_kernel(SweepParams<T> P)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    pcd_solve<T, WLDS, RPT, 2>(P, blockIdx.x, gridDim.x, smem_raw);
+}
+
+// Many independent problems in one launch: workgroup blockIdx.x serves
+// problem wg_problem[blockIdx.x], as workgroup blockIdx.x - g0 of its Gr x Gc.
+// W stays in HBM here (one code path keeps the register budget of the
+// single-problem kernel; the problems of a batch are small enough for their
+// W rows to stay in L2 and the last-level cache anyway).  A batch gives each
+// problem few workgroups, so row rewrites are a large part of each colour
+// step: they keep four columns per lane in flight instead of two.
+template <typename T>
+__global__ void __launch_bounds__(512)
+    pcd_batched_kernel(const SweepParams<T> *__restrict__ descs, const int *__restrict__ wg_problem)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const SweepParams<T> P = descs[wg_problem[blockIdx.x]];
+    const int g = (int)blockIdx.x - P.g0, G = P.Gr * P.Gc;
+    pcd_solve<T, false, 2, 4>(P, g, G, smem_raw);
 }
 
 namespace {
@@ -596,6 +735,24 @@ hipError_t launch_sweep(const SweepParams<T> &P, int threads, hipStream_t stream
     return hipLaunchCooperativeKernel(fn, dim3(G), dim3(threads), args, (unsigned)lds, stream);
 }
 
+template <typename T>
+hipError_t launch_sweep_batched(const SweepParams<T> *descs, const int *wg_problem, int G,
+                                size_t lds, int threads, hipStream_t stream)
+{
+    const void *fn = (const void *)pcd_batched_kernel<T>;
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess)
+        return e;
+    void *args[] = {&descs, &wg_problem};
+    if (G == 1)
+        return hipLaunchKernel(fn, dim3(1), dim3(threads), args, lds, stream);
+    return hipLaunchCooperativeKernel(fn, dim3(G), dim3(threads), args, (unsigned)lds, stream);
+}
+
+template hipError_t launch_sweep_batched<float>(const SweepParams<float> *, const int *, int,
+                                                size_t, int, hipStream_t);
+template hipError_t launch_sweep_batched<double>(const SweepParams<double> *, const int *, int,
+                                                 size_t, int, hipStream_t);
 template size_t sweep_lds_bytes<float>(const SweepParams<float> &);
 template size_t sweep_lds_bytes<double>(const SweepParams<double> &);
 template hipError_t launch_sweep<float>(const SweepParams<float> &, int, hipStream_t);

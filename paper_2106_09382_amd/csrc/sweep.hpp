@@ -27,6 +27,18 @@ namespace concord {
 //         [4] input error bits from the set-up kernels
 // Entries of pc (colours >= 1) and pd are reset to a signalling-NaN sentinel
 // one sweep before they are written; a reader polls until the sentinel is gone.
+// Summary of one lambda of a path, written by the sweep kernel: the sweep
+// count at which the lambda finished (counted from the start of the path),
+// whether its convergence test passed, nonzeros above the diagonal, the
+// objective of the Omega it left, and when it started and ended.
+struct PathRec {
+    unsigned long long nnz_upper;
+    double objective;
+    int t_end;
+    int converged;
+    unsigned long long clock_start, clock_end;  // device clock (100 MHz) around the lambda
+};
+
 template <typename T>
 struct SweepParams {
     const T *S;
@@ -53,6 +65,16 @@ struct SweepParams {
     long long spin_limit;
     unsigned long long *tstamp;  // optional: [G][tstamp_steps][3] device timestamps
     int tstamp_steps;
+    // Lambda path (batched solves): L values lams[0..L-1] run one after the
+    // other, each warm-started from the previous; red then holds L * maxit
+    // sweeps.  omega_out[l] (device pointers) receives the dense Omega of
+    // lambda l and rec[l] its summary.  L = 1 with lams, omega_out and rec
+    // null is a single solve at lam.
+    int L;
+    const double *lams;
+    T *const *omega_out;
+    PathRec *rec;
+    int g0;  // first workgroup of this problem in a batched launch
 };
 
 // Column slice b of Gc over p columns: [slice_lo(b), slice_lo(b + 1)).
@@ -77,5 +99,12 @@ size_t sweep_lds_bytes(const SweepParams<T> &P);
 
 template <typename T>
 hipError_t launch_sweep(const SweepParams<T> &P, int threads, hipStream_t stream);
+
+// One cooperative launch over G workgroups serving several problems:
+// descs (device) holds one SweepParams per problem, wg_problem (device, G
+// entries) the problem of each workgroup; lds = the largest sweep_lds_bytes.
+template <typename T>
+hipError_t launch_sweep_batched(const SweepParams<T> *descs, const int *wg_problem, int G,
+                                size_t lds, int threads, hipStream_t stream);
 
 }  // namespace concord

@@ -89,3 +89,35 @@ def test_gram_rejects_bad_sizes(lib):
     assert lib.concord_gram(None, 10, 10, 1, ctypes.c_void_p(0x10), None) == -1
     assert lib.concord_gram(ctypes.c_void_p(0x10), 0, 10, 1, ctypes.c_void_p(0x10), None) == -1
     assert lib.concord_gram(ctypes.c_void_p(0x10), 10, 10, 3, ctypes.c_void_p(0x10), None) == -1
+
+
+def _fit_batched(lib, B=2, L=3, **kw):
+    from paper_2106_09382_amd import _lib
+    vp = ctypes.c_void_p
+    a = dict(B=B, kind=0, X=(vp * B)(*([0x1000] * B)), n=None, p=(ctypes.c_int64 * B)(*([8] * B)),
+             L=L, lam=(ctypes.c_double * (B * L))(*([0.1] * (B * L))), tol=1e-6, maxit=10, dt=1,
+             omega=(vp * (B * L))(*([0x2000] * (B * L))))
+    a.update(kw)
+    return lib.concord_fit_batched(a["B"], a["kind"], a["X"], a["n"], a["p"], a["L"], a["lam"],
+                                   a["tol"], a["maxit"], a["dt"], a["omega"], None, None)
+
+
+def test_batched_invalid_arguments_return_einval(lib):
+    vp = ctypes.c_void_p
+    assert _fit_batched(lib, B=0) == -1
+    assert _fit_batched(lib, L=0) == -1
+    assert _fit_batched(lib, X=None) == -1
+    assert _fit_batched(lib, p=None) == -1
+    assert _fit_batched(lib, lam=None) == -1
+    assert _fit_batched(lib, omega=None) == -1
+    assert _fit_batched(lib, kind=1, n=None) == -1
+    assert _fit_batched(lib, kind=1, n=(ctypes.c_int64 * 2)(4, 0)) == -1
+    assert _fit_batched(lib, p=(ctypes.c_int64 * 2)(8, 0)) == -1
+    assert _fit_batched(lib, X=(vp * 2)(0x1000, None)) == -1
+    assert _fit_batched(lib, lam=(ctypes.c_double * 6)(0.5, 0.2, 0.1, 0.5, float("nan"), 0.1)) == -1
+    assert _fit_batched(lib, lam=(ctypes.c_double * 6)(0.5, 0.2, 0.1, 0.5, -1.0, 0.1)) == -1
+    assert _fit_batched(lib, omega=(vp * 6)(0x2000, 0x2000, 0x2000, 0x2000, 0x2000, None)) == -1
+    assert _fit_batched(lib, tol=0.0) == -1
+    assert _fit_batched(lib, maxit=0) == -1
+    assert _fit_batched(lib, L=3, maxit=(1 << 23)) == -1  # L * maxit > 2^24
+    assert _fit_batched(lib, dt=5) == -1

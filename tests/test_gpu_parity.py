@@ -113,6 +113,35 @@ def test_config1_bitwise_identical_across_shapes_and_runs(lib):
     assert np.array_equal(again, ref)
 
 
+W_SHAPES = [
+    dict(),
+    dict(pending_depth=2),
+    dict(pending_depth=5),
+    dict(row_groups=4, col_slices=2, pending_depth=6),
+    dict(row_groups=8, col_slices=1, w_in_lds=2, pending_depth=8),
+    dict(row_groups=1, col_slices=2, block_threads=128, w_in_lds=2, pending_depth=3),
+]
+
+
+@pytest.mark.parametrize("maxit", [1, 3, 500])
+@pytest.mark.parametrize("shape", W_SHAPES, ids=[str(s) for s in W_SHAPES])
+def test_stored_product_is_omega_s(lib, shape, maxit):
+    # The kernel keeps W = Omega S with deferred row updates; after the last
+    # sweep every pending update must be in the stored rows.  Exact up to the
+    # rounding of the accumulated fused multiply-adds.
+    pr = _problem(1)
+    S = pr["S"]
+    St = torch.tensor(S, device="cuda")
+    Wt = torch.full_like(St, float("nan"))
+    om, info = lib.fit(St, 0.3, 1e-8, maxit, check=False, w_out=Wt, **shape)
+    torch.cuda.synchronize()
+    got = om.cpu().numpy()
+    W = Wt.cpu().numpy()
+    assert info["code"] in (0, 1)
+    scale = (np.abs(got) @ np.abs(S)).max()
+    assert np.abs(W - got @ S).max() <= 1e-13 * scale * max(info["sweeps"], 1)
+
+
 # ------------------------------------------------------------------ ragged sizes
 
 RAGGED = [1, 2, 3, 4, 5, 6, 7, 16, 31, 33, 64, 65, 96, 97, 128, 129, 200, 257, 300]
@@ -141,6 +170,26 @@ def test_two_rows_per_thread(lib, wl):
     got, ginfo = _gpu_fit(lib, pr["S"], 0.15, 1e-9, 2000, row_groups=1, col_slices=2,
                           block_threads=64, w_in_lds=wl, pending_depth=3)
     _assert_parity64(pr["S"], got, ginfo, want, winfo, 0.15)
+
+
+@pytest.mark.parametrize("wl", [1, 2])
+def test_rows_spread_over_waves(lib, wl):
+    # 100 rows in one row group on two waves of 50 rows each.
+    pr = _problem(2, p=100, n=150)
+    want, winfo, _ = _oracle(pr, 0.15, 1e-9, 2000)
+    got, ginfo = _gpu_fit(lib, pr["S"], 0.15, 1e-9, 2000, row_groups=1, col_slices=2,
+                          block_threads=128, w_in_lds=wl, pending_depth=3)
+    _assert_parity64(pr["S"], got, ginfo, want, winfo, 0.15)
+
+
+def test_long_logs_many_chunks(lib):
+    # W in HBM, one column slice (many column chunks per row rewrite) and a
+    # deep list of pending row updates.
+    pr = _problem(2, p=300, n=150)
+    want, winfo, _ = _oracle(pr, 0.05, 1e-9, 3000)
+    got, ginfo = _gpu_fit(lib, pr["S"], 0.05, 1e-9, 3000, row_groups=8, col_slices=1,
+                          block_threads=64, w_in_lds=2, pending_depth=6)
+    _assert_parity64(pr["S"], got, ginfo, want, winfo, 0.05)
 
 
 @pytest.mark.parametrize("p", [5, 64, 129, 257])
