@@ -15,6 +15,9 @@ write them).  The helpers here are plain NumPy definitions:
 * ``kkt``: stationarity of F.  With G = Omega S + S Omega, an optimum has
   omega_ii (S Omega)_ii = 1, G_ij + lam sign(omega_ij) = 0 where omega_ij != 0,
   and |G_ij| <= lam where omega_ij = 0.
+
+``oracle.backward`` holds the implicit gradient of the estimate (dL/dS and
+dL/dlam from the stationarity system on the active set, by a dense solve).
 """
 from __future__ import annotations
 
