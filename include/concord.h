@@ -175,6 +175,45 @@ int concord_fit_batched_ex(int32_t B, concord_input kind, const void *const *X, 
                            concord_info *info, void *stream, const concord_batch_options *opts);
 
 /*
+ * concord_backward -- implicit gradient of the estimate (for training losses
+ * and lambda tuning through a fit).  Given Omega-hat = concord_fit(S, lam)
+ * and C = dL/dOmega-hat, returns dL/dS and dL/dlam.
+ *
+ * At Omega-hat the stationarity conditions of eq. (1) on the free entries
+ * (the diagonal, and the pairs i < j with omega_ij != 0; the others stay 0
+ * under small changes) are R_ii = (Omega S)_ii - 1/omega_ii = 0 and
+ * R_ij = (Omega S)_ij + (Omega S)_ji + lam sign(omega_ij) = 0.  The adjoint
+ * system J^T v = dL/dtheta (J = dR/dtheta, symmetric) is solved by coloured
+ * Gauss-Seidel sweeps on the schedule of Algorithm 1 (pairs of a colour are
+ * independent, as in Lemma 2); then
+ *   dL/dS   = -(Omega V + V Omega) / 2   (V: v as a symmetric matrix),
+ *   dL/dlam = -sum_{i<j free} v_ij sign(omega_ij).
+ * The system does not involve lam itself.
+ *   S           p x p device matrix the fit used (S_ii > 0)
+ *   omega_hat   p x p device matrix, the fit's output (symmetric, omega_ii > 0)
+ *   grad_omega  p x p device matrix dL/dOmega-hat (any matrix; omega_ij and
+ *               omega_ji are one unknown, so C_ij + C_ji is what counts)
+ *   grad_S      out, p x p device matrix, the symmetric gradient: dL =
+ *               sum_ab grad_S_ab dS_ab for every symmetric change dS
+ *   grad_lambda out, host pointer (may be NULL)
+ *   tol, maxit  Gauss-Seidel stopping rule: max |change of v| over a sweep
+ *               < tol (FP32: tol_eff = max(tol, 16 eps max_i |v_ii|)), at
+ *               most maxit sweeps
+ *   info        out (host, may be NULL): sweeps, status, delta, tol_eff, times
+ * Returns CONCORD_OK, CONCORD_NOT_CONVERGED (outputs from the last sweep), or
+ * a negative code (CONCORD_ENOTPD when some omega_ii or S_ii is not positive).
+ */
+int concord_backward(const void *S, const void *omega_hat, int64_t p, const void *grad_omega,
+                     void *grad_S, double *grad_lambda, double tol, int32_t maxit,
+                     concord_dtype dt, concord_info *info, void *stream);
+
+/* concord_backward with explicit launch options (opts may be NULL). */
+int concord_backward_ex(const void *S, const void *omega_hat, int64_t p, const void *grad_omega,
+                        void *grad_S, double *grad_lambda, double tol, int32_t maxit,
+                        concord_dtype dt, concord_info *info, void *stream,
+                        const concord_options *opts);
+
+/*
  * concord_gram -- S = Y^T Y / n (the T = X^T X of Algorithm 1's set-up, on
  * the S scale), computed with matrix-core (MFMA) instructions.
  *   Y  n x p device matrix, S  p x p device output (both triangles written).

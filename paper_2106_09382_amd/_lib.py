@@ -108,6 +108,12 @@ def load(path: str = LIB_PATH):
     lib.concord_fit_batched_ex.restype = ctypes.c_int
     lib.concord_fit_batched.argtypes = lib.concord_fit_batched_ex.argtypes[:-1]
     lib.concord_fit_batched.restype = ctypes.c_int
+    lib.concord_backward_ex.argtypes = [vp, vp, i64, vp, vp, ctypes.POINTER(dbl), dbl, i32,
+                                        ctypes.c_int, ctypes.POINTER(ConcordInfo), vp,
+                                        ctypes.POINTER(ConcordOptions)]
+    lib.concord_backward_ex.restype = ctypes.c_int
+    lib.concord_backward.argtypes = lib.concord_backward_ex.argtypes[:-1]
+    lib.concord_backward.restype = ctypes.c_int
     lib.concord_gram.argtypes = [vp, i64, i64, ctypes.c_int, vp, vp]
     lib.concord_gram.restype = ctypes.c_int
     lib.concord_schedule.argtypes = [i64, ctypes.POINTER(ctypes.c_int32)]
@@ -290,6 +296,41 @@ def fit_batched(Xs, lambdas, tol: float = 1e-6, maxit: int = 500, *, kind: str =
     if check:
         _raise(code, "concord_fit_batched")
     return outs, di, code
+
+
+def backward(S: torch.Tensor, omega: torch.Tensor, grad_omega: torch.Tensor, tol: float = 1e-10,
+             maxit: int = 2000, *, out: torch.Tensor | None = None, stream=None,
+             row_groups: int = 0, col_slices: int = 0, block_threads: int = 0,
+             w_in_lds: int = 0, pending_depth: int = 0, check: bool = True):
+    """Implicit gradient of Omega-hat = fit(S, lam): returns (dL/dS, dL/dlam, info)
+    for dL/dOmega-hat = grad_omega.  dL/dS is the symmetric gradient."""
+    lib = load()
+    for t, name in ((S, "S"), (omega, "omega"), (grad_omega, "grad_omega")):
+        _check_dev(t, name)
+        if t.dtype != S.dtype or t.dim() != 2 or t.shape[0] != t.shape[1] \
+                or t.shape[0] != S.shape[0]:
+            raise ValueError(f"{name} must be p x p with S's dtype")
+    p = S.shape[0]
+    dt = _dtype_code(S)
+    if out is None:
+        out = torch.empty((p, p), dtype=S.dtype, device=S.device)
+    _check_dev(out, "out")
+    info = ConcordInfo()
+    gl = ctypes.c_double(0.0)
+    opts = ConcordOptions(row_groups, col_slices, block_threads, w_in_lds, pending_depth, None,
+                          None, 0, 0, None)
+    with torch.cuda.device(S.device):
+        code = lib.concord_backward_ex(ctypes.c_void_p(S.data_ptr()),
+                                       ctypes.c_void_p(omega.data_ptr()), p,
+                                       ctypes.c_void_p(grad_omega.data_ptr()),
+                                       ctypes.c_void_p(out.data_ptr()), ctypes.byref(gl),
+                                       float(tol), int(maxit), dt, ctypes.byref(info),
+                                       _stream_handle(stream), ctypes.byref(opts))
+    d = info.as_dict()
+    d["code"] = code
+    if check:
+        _raise(code, "concord_backward")
+    return out, gl.value, d
 
 
 def gram(Y: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:

@@ -352,6 +352,181 @@ int fit_impl(concord_input kind, const void *X, int64_t n64, int64_t p64, double
     return status;
 }
 
+// ---------------------------------------------------------------- backward
+
+// Implicit gradient at Omega-hat: set up the adjoint system (v = 0, U = V S =
+// 0, right-hand side from grad_omega), solve it with the sweep kernel in its
+// adjoint mode, then dL/dS = -(Omega V + V Omega)/2 (Omega V by the matrix-core
+// product) and dL/dlam = -sum_{i<j} v_ij sign(omega_ij).
+template <typename T>
+int backward_impl(const void *Sv, const void *omv, int64_t p64, const void *Cv, void *gSv,
+                  double *grad_lambda, double tol, int32_t maxit, concord_info *info,
+                  hipStream_t stream, const concord_options *opts)
+{
+    const int p = (int)p64;
+    Shape sh;
+    int rc = choose_shape<T>(p, opts, &sh);
+    if (rc)
+        return rc;
+    const Circle C = Circle::make(p);
+    const int G = sh.Gr * sh.Gc;
+    hipEvent_t ev[4] = {};
+    struct EvGuard {
+        hipEvent_t *e;
+        ~EvGuard()
+        {
+            for (int k = 0; k < 4; ++k)
+                if (e[k])
+                    (void)hipEventDestroy(e[k]);
+        }
+    } evg{ev};
+    for (int k = 0; k < 4; ++k)
+        CK_HIP(hipEventCreate(&ev[k]));
+    CK_HIP(hipEventRecord(ev[0], stream));
+
+    Carver cv;
+    const size_t pp = (size_t)p * p;
+    const size_t oW = cv.take<T>(pp);
+    const size_t oVp = cv.take<T>((size_t)G * C.m * sh.nr_max);
+    const size_t oVdp = cv.take<T>((size_t)G * sh.nr_max);
+    const size_t oAg = cv.take<T>((size_t)G * C.m * sh.nr_max);
+    const size_t oAgd = cv.take<T>((size_t)G * sh.nr_max);
+    const size_t oAhd = cv.take<T>((size_t)G * sh.nr_max);
+    const size_t oSd = cv.take<T>(p);
+    const size_t PS = (size_t)sh.Gr * sh.nr_max;
+    const size_t oPc = cv.take<T>(2 * (size_t)C.m * PS);
+    const size_t oPd = cv.take<T>(2 * PS);
+    const size_t oFlags = cv.take<unsigned>(G);
+    const size_t oRed = cv.take<unsigned long long>(4 * (size_t)maxit);
+    const size_t oOut = cv.take<int>(kOutWords);
+    const size_t oAcc = cv.take<double>(4);
+    const size_t oV = cv.take<T>(pp);
+    const size_t oM = cv.take<T>(pp);
+    Workspace ws;
+    ws.stream = stream;
+    ws.bytes = cv.off;
+    {
+        hipError_t e = hipMallocAsync(&ws.base, ws.bytes, stream);
+        if (e != hipSuccess) {
+            ws.base = nullptr;
+            return map_hip(e);
+        }
+    }
+    char *B = (char *)ws.base;
+    const T *S = (const T *)Sv, *om = (const T *)omv, *Cg = (const T *)Cv;
+    T *W = (T *)(B + oW), *vp = (T *)(B + oVp), *vdp = (T *)(B + oVdp);
+    T *adj_g = (T *)(B + oAg), *adj_gd = (T *)(B + oAgd), *adj_hd = (T *)(B + oAhd);
+    T *sd = (T *)(B + oSd), *pc = (T *)(B + oPc), *pd = (T *)(B + oPd);
+    T *V = (T *)(B + oV), *M = (T *)(B + oM);
+    unsigned *flags = (unsigned *)(B + oFlags);
+    unsigned long long *red = (unsigned long long *)(B + oRed);
+    int *out = (int *)(B + oOut);
+    double *acc = (double *)(B + oAcc);
+
+    CK_HIP(launch_clear(flags, G, red, 4 * maxit, out, kOutWords, acc, 4, stream));
+    CK_HIP(launch_check_copy<T>(S, p, W, false, sd, out + 4, stream));
+    CK_HIP(launch_fill<T>(W, (long long)pp, T(0), stream));
+    CK_HIP(launch_init_adjoint<T>(om, Cg, sd, p, sh.Gr, sh.Gc, sh.nr_max, vp, vdp, adj_g, adj_gd,
+                                  adj_hd, out + 4, stream));
+    CK_HIP(launch_init_publish<T>(W, p, sh.Gr, sh.nr_max, pc, pd, stream));
+
+    SweepParams<T> P;
+    memset(&P, 0, sizeof(P));
+    P.S = S;
+    P.sd = sd;
+    P.W = W;
+    P.omp = vp;
+    P.omdp = vdp;
+    P.pc = pc;
+    P.pd = pd;
+    P.flags = flags;
+    P.red = red;
+    P.out = out;
+    P.p = p;
+    P.Gr = sh.Gr;
+    P.Gc = sh.Gc;
+    P.maxit = maxit;
+    P.w_lds = sh.w_lds;
+    P.nr_max = sh.nr_max;
+    P.nc_max = sh.nc_max;
+    P.depth = sh.depth;
+    P.rpt = sh.rpt;
+    P.tol = (T)tol;
+    P.tol_coef = (sizeof(T) == 4) ? T(16.0 * 1.1920928955078125e-07) : T(0);
+    P.spin_limit = kSpinLimit;
+    P.adj_g = adj_g;
+    P.adj_gd = adj_gd;
+    P.adj_hd = adj_hd;
+    CK_HIP(hipEventRecord(ev[1], stream));
+    CK_HIP(launch_sweep<T>(P, sh.threads, stream));
+    CK_HIP(hipEventRecord(ev[2], stream));
+    CK_HIP(launch_gather<T>(vp, vdp, sh.Gr, sh.Gc, sh.nr_max, p, V, stream));
+    CK_HIP(launch_atb<T>(om, V, p, p, p, M, stream));
+    CK_HIP(launch_adjoint_output<T>(M, V, om, p, (T *)gSv, acc, out + 4, stream));
+    CK_HIP(hipEventRecord(ev[3], stream));
+
+    int hout[kOutWords];
+    double hacc = 0.0;
+    std::vector<unsigned long long> hred(4 * (size_t)maxit);
+    CK_HIP(hipMemcpyAsync(hout, out, sizeof(hout), hipMemcpyDeviceToHost, stream));
+    CK_HIP(hipMemcpyAsync(&hacc, acc, sizeof(double), hipMemcpyDeviceToHost, stream));
+    CK_HIP(hipMemcpyAsync(hred.data(), red, sizeof(unsigned long long) * hred.size(),
+                          hipMemcpyDeviceToHost, stream));
+    CK_HIP(hipStreamSynchronize(stream));
+    float ms = 0.f, ms_sweep = 0.f;
+    (void)hipEventElapsedTime(&ms, ev[0], ev[3]);
+    (void)hipEventElapsedTime(&ms_sweep, ev[1], ev[2]);
+    const int sweeps = hout[0];
+    auto bits_to = [](unsigned long long u) -> double {
+        if (sizeof(T) == 8) {
+            double d;
+            memcpy(&d, &u, 8);
+            return d;
+        }
+        uint32_t w = (uint32_t)u;
+        float f;
+        memcpy(&f, &w, 4);
+        return (double)f;
+    };
+    int status;
+    if (hout[4] & kErrNotPD)
+        status = CONCORD_ENOTPD;
+    else if (hout[4] & kErrNonFinite)
+        status = CONCORD_ENONFINITE;
+    else if (hout[2] || hout[3])
+        status = CONCORD_EDEVICE;
+    else
+        status = hout[1] ? CONCORD_OK : CONCORD_NOT_CONVERGED;
+    if (grad_lambda)
+        *grad_lambda = hacc;
+    if (info) {
+        memset(info, 0, sizeof(*info));
+        info->sweeps = sweeps;
+        info->status = status;
+        if (sweeps > 0) {
+            info->delta = bits_to(hred[4 * (size_t)(sweeps - 1)]);
+            info->tol_eff = std::max(tol, (double)P.tol_coef * bits_to(hred[4 * (size_t)(sweeps - 1) + 1]));
+        } else {
+            info->tol_eff = tol;
+        }
+        int64_t mv = 0, mvd = 0;
+        for (int t = 0; t < sweeps && t < maxit; ++t) {
+            mv += (int64_t)hred[4 * (size_t)t + 2];
+            mvd += (int64_t)hred[4 * (size_t)t + 3];
+        }
+        info->elapsed_ms = ms;
+        info->sweep_ms = ms_sweep;
+        info->moved_pairs = mv;
+        info->moved_diag = mvd;
+        info->row_groups = sh.Gr;
+        info->col_slices = sh.Gc;
+        info->w_in_lds = sh.w_lds;
+        info->block_threads = sh.threads;
+        info->pending_depth = sh.depth;
+    }
+    return status;
+}
+
 // ---------------------------------------------------------------- batched
 
 // Status of a batch: the first negative code met, else NOT_CONVERGED if any
@@ -794,6 +969,40 @@ extern "C" int concord_fit_batched(int32_t B, concord_input kind, const void *co
 {
     return concord_fit_batched_ex(B, kind, X, n, p, L, lambdas, tol, maxit, dt, omega, info,
                                   stream, nullptr);
+}
+
+extern "C" int concord_backward_ex(const void *S, const void *omega_hat, int64_t p,
+                                   const void *grad_omega, void *grad_S, double *grad_lambda,
+                                   double tol, int32_t maxit, concord_dtype dt, concord_info *info,
+                                   void *stream, const concord_options *opts)
+{
+    int rc = CONCORD_OK;
+    if (!S || !omega_hat || !grad_omega || !grad_S)
+        rc = CONCORD_EINVAL;
+    else
+        rc = validate(CONCORD_INPUT_S, S, 1, p, 0.0, tol, maxit, dt, grad_S);
+    if (rc) {
+        if (info) {
+            memset(info, 0, sizeof(*info));
+            info->status = rc;
+        }
+        return rc;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    if (dt == CONCORD_F64)
+        return backward_impl<double>(S, omega_hat, p, grad_omega, grad_S, grad_lambda, tol, maxit,
+                                     info, st, opts);
+    return backward_impl<float>(S, omega_hat, p, grad_omega, grad_S, grad_lambda, tol, maxit,
+                                info, st, opts);
+}
+
+extern "C" int concord_backward(const void *S, const void *omega_hat, int64_t p,
+                                const void *grad_omega, void *grad_S, double *grad_lambda,
+                                double tol, int32_t maxit, concord_dtype dt, concord_info *info,
+                                void *stream)
+{
+    return concord_backward_ex(S, omega_hat, p, grad_omega, grad_S, grad_lambda, tol, maxit, dt,
+                               info, stream, nullptr);
 }
 
 extern "C" int concord_gram(const void *Y, int64_t n, int64_t p, concord_dtype dt, void *S,

@@ -24,4 +24,18 @@ hipError_t launch_finalize(const T *omp, const T *omdp, int Gr, int Gc, int NR, 
                            T lam, T *omega, double *acc, unsigned long long *nnz, int *err,
                            hipStream_t st);
 
+// Adjoint system of the implicit gradient (adjoint.hip).
+template <typename T>
+hipError_t launch_init_adjoint(const T *om, const T *C, const T *sd, int p, int Gr, int Gc, int NR,
+                               T *vp, T *vdp, T *adj_g, T *adj_gd, T *adj_hd, int *err,
+                               hipStream_t st);
+template <typename T>
+hipError_t launch_fill(T *x, long long n, T v, hipStream_t st);
+template <typename T>
+hipError_t launch_gather(const T *vp, const T *vdp, int Gr, int Gc, int NR, int p, T *V,
+                         hipStream_t st);
+template <typename T>
+hipError_t launch_adjoint_output(const T *M, const T *V, const T *om, int p, T *gS, double *acc,
+                                 int *err, hipStream_t st);
+
 }  // namespace concord

@@ -184,6 +184,7 @@ struct RowNext {
     bool last;    // the step is the last colour (diagonal step follows)
     bool pubd;    // the step publishes W_ii for the following last colour
     T w, od, s_ji, wb, s_jn, s_in;
+    T g;          // adjoint mode: right-hand side of the pair (NaN: pair not free)
     T sv[kMaxDepth];
 };
 
@@ -192,7 +193,8 @@ __device__ __forceinline__ void load_next(RowNext<T> &x, const Circle &C, int r1
                                           int n, const int *pj, int D, int NR, int p, int c0,
                                           int c1, int nc, const T *__restrict__ S,
                                           const T *__restrict__ Wg, const T *wblk,
-                                          const T *__restrict__ omp, const T *__restrict__ omdp)
+                                          const T *__restrict__ omp, const T *__restrict__ omdp,
+                                          const T *__restrict__ adjg)
 {
     const int m = C.m;
     const int rn1 = (r1 + 1 == m) ? 0 : r1 + 1;
@@ -203,6 +205,7 @@ __device__ __forceinline__ void load_next(RowNext<T> &x, const Circle &C, int r1
     x.pubd = (rn1 == m - 1) && i >= c0 && i < c1;
     x.n = n;
     x.w = (x.j >= 0) ? omp[(size_t)r1 * NR + k] : T(0);
+    x.g = (adjg && x.j >= 0) ? adjg[(size_t)r1 * NR + k] : T(0);
     x.od = x.last ? omdp[k] : T(0);
     x.s_ji = (x.j >= 0 && (x.last || x.pubd)) ? S[(size_t)x.j * p + i] : T(0);
     if (x.kn >= 0) {
@@ -302,7 +305,23 @@ __device__ void end_of_lambda(const SweepParams<T> &P, int l, T lam, const Circl
 
 // One solve (a whole lambda path) by workgroup g of the G workgroups that
 // share the problem described by P.  CPL: columns per lane in row rewrites.
-template <typename T, bool WLDS, int RPT, int CPL>
+//
+// ADJ selects the adjoint system of the implicit gradient instead of the
+// estimate.  At Omega-hat the stationarity conditions on the free entries
+// (the diagonal, and the pairs with omega_ij != 0) have the symmetric Jacobian
+//   (J v)_ij = U_ij + U_ji,   (J v)_ii = U_ii + v_ii / omega_ii^2,   U = V S,
+// with V the symmetric matrix of the unknowns v (0 off the free pairs): the
+// same structure as eqs. (2)-(3) with U in place of W.  Gauss-Seidel on
+// J v = g in the colour order is therefore this same sweep with linear
+// coordinate updates,
+//   v_ij <- (g_ij - (U_ij + U_ji - (S_ii + S_jj) v_ij)) / (S_ii + S_jj),
+//   v_ii <- (g_ii - (U_ii - S_ii v_ii)) / (S_ii + 1 / omega_ii^2),
+// a pair outside the active set keeping v_ij = 0; pairs of one colour share
+// no vertex, so they are independent as in Lemma 2.  The buffers W, omp and
+// omdp then hold U and v; P.adj_g holds g_ij per colour in omp's layout (NaN
+// for a pair that is not free) and P.adj_gd / P.adj_hd hold g_ii and
+// S_ii + 1/omega_ii^2 per row.
+template <typename T, bool WLDS, int RPT, int CPL, bool ADJ>
 __device__ void pcd_solve(const SweepParams<T> &P, int g, int G, unsigned char *smem_raw)
 {
     using U = typename Sentinel<T>::U;
@@ -336,6 +355,7 @@ __device__ void pcd_solve(const SweepParams<T> &P, int g, int G, unsigned char *
     T *__restrict__ Wg = P.W;
     T *__restrict__ omp = P.omp + (size_t)g * m * NR;
     T *__restrict__ omdp = P.omdp + (size_t)g * NR;
+    const T *__restrict__ adjg = ADJ ? P.adj_g + (size_t)g * m * NR : nullptr;
 
     for (int k = tid; k < NR; k += nthr)
         np[k] = 0;
@@ -365,7 +385,15 @@ __device__ void pcd_solve(const SweepParams<T> &P, int g, int G, unsigned char *
         const int k = tid + u * nthr;
         if (k < nr)
             load_next<T, WLDS>(nx[u], C, 0, a + k * Gr, k, 0, pj, D, NR, p, c0, c1, nc, S, Wg,
-                               wblk, omp, omdp);
+                               wblk, omp, omdp, adjg);
+    }
+    // adjoint mode: the diagonal right-hand side and denominator of each row
+    T adj_gd[RPT], adj_hd[RPT];
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) {
+        const int k = tid + u * nthr;
+        adj_gd[u] = (ADJ && k < nr) ? P.adj_gd[(size_t)g * NR + k] : T(0);
+        adj_hd[u] = (ADJ && k < nr) ? P.adj_hd[(size_t)g * NR + k] : T(1);
     }
     unsigned step = 0;
 
@@ -494,7 +522,11 @@ __device__ void pcd_solve(const SweepParams<T> &P, int g, int G, unsigned char *
                     const int lo = j < i ? j : i, hi = j < i ? i : j;
                     const T sden = sd[lo] + sd[hi];
                     const T bnum = fma(-sden, x.w, as_value<T>(blo) + as_value<T>(bhi));
-                    const T wn = soft_threshold(-bnum, lam) / sden;
+                    T wn;
+                    if (ADJ)
+                        wn = (x.g == x.g) ? (x.g - bnum) / sden : x.w;
+                    else
+                        wn = soft_threshold(-bnum, lam) / sden;
                     del = wn - x.w;
                     if (del != T(0))
                         omp[(size_t)r * NR + k] = wn;
@@ -505,13 +537,19 @@ __device__ void pcd_solve(const SweepParams<T> &P, int g, int G, unsigned char *
                         wii = fma(del, x.s_ji, wii);
                     const T sii = sd[i];
                     const T c = fma(-sii, x.od, wii);
-                    const T disc = sqrt(fma(c, c, T(4) * sii));
-                    // eq. (2); for c >= 0 the same root is 2 / (c + disc) without cancellation.
-                    const T on = (c >= T(0)) ? T(2) / (c + disc) : (disc - c) / (T(2) * sii);
+                    T on;
+                    if (ADJ) {
+                        on = (adj_gd[u] - c) / adj_hd[u];
+                    } else {
+                        const T disc = sqrt(fma(c, c, T(4) * sii));
+                        // eq. (2); for c >= 0 the same root is 2 / (c + disc) without cancellation.
+                        on = (c >= T(0)) ? T(2) / (c + disc) : (disc - c) / (T(2) * sii);
+                    }
                     dd = on - x.od;
                     if (dd != T(0))
                         omdp[k] = on;
-                    gloc = (on > gloc || on != on) ? on : gloc;
+                    const T gv = ADJ ? fabs(on) : on;
+                    gloc = (gv > gloc || gv != gv) ? gv : gloc;
                 }
 
                 // ---- record the changes as pending updates of row i
@@ -561,7 +599,7 @@ __device__ void pcd_solve(const SweepParams<T> &P, int g, int G, unsigned char *
                 // read before this step's rewrites (they start after the
                 // workgroup barrier below), so it is folded with all n entries.
                 load_next<T, WLDS>(nx[u], C, rn, i, k, n, pj, D, NR, p, c0, c1, nc, S, Wg, wblk,
-                                   omp, omdp);
+                                   omp, omdp, adjg);
             }
 
             // ---- every row of the step is done; rewrite the rows whose lists are full
@@ -683,11 +721,11 @@ size_t sweep_lds_bytes(const SweepParams<T> &P)
     return bytes;
 }
 
-template <typename T, bool WLDS, int RPT>
+template <typename T, bool WLDS, int RPT, bool ADJ>
 __global__ void __launch_bounds__(512) pcd_sweep_kernel(SweepParams<T> P)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    pcd_solve<T, WLDS, RPT, 2>(P, blockIdx.x, gridDim.x, smem_raw);
+    pcd_solve<T, WLDS, RPT, 2, ADJ>(P, blockIdx.x, gridDim.x, smem_raw);
 }
 
 // Many independent problems in one launch: workgroup blockIdx.x serves
@@ -704,17 +742,17 @@ __global__ void __launch_bounds__(512)
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const SweepParams<T> P = descs[wg_problem[blockIdx.x]];
     const int g = (int)blockIdx.x - P.g0, G = P.Gr * P.Gc;
-    pcd_solve<T, false, 2, 4>(P, g, G, smem_raw);
+    pcd_solve<T, false, 2, 4, false>(P, g, G, smem_raw);
 }
 
 namespace {
 
-template <typename T, bool WLDS>
+template <typename T, bool WLDS, bool ADJ>
 const void *pick_kernel(int rpt)
 {
     if (rpt <= 1)
-        return (const void *)pcd_sweep_kernel<T, WLDS, 1>;
-    return (const void *)pcd_sweep_kernel<T, WLDS, 2>;
+        return (const void *)pcd_sweep_kernel<T, WLDS, 1, ADJ>;
+    return (const void *)pcd_sweep_kernel<T, WLDS, 2, ADJ>;
 }
 
 }  // namespace
@@ -726,7 +764,11 @@ hipError_t launch_sweep(const SweepParams<T> &P, int threads, hipStream_t stream
     const int G = P.Gr * P.Gc;
     SweepParams<T> arg = P;
     void *args[] = {&arg};
-    const void *fn = P.w_lds ? pick_kernel<T, true>(P.rpt) : pick_kernel<T, false>(P.rpt);
+    const void *fn;
+    if (P.adj_g)
+        fn = P.w_lds ? pick_kernel<T, true, true>(P.rpt) : pick_kernel<T, false, true>(P.rpt);
+    else
+        fn = P.w_lds ? pick_kernel<T, true, false>(P.rpt) : pick_kernel<T, false, false>(P.rpt);
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess)
         return e;

@@ -75,6 +75,12 @@ struct SweepParams {
     T *const *omega_out;
     PathRec *rec;
     int g0;  // first workgroup of this problem in a batched launch
+    // Adjoint system of the implicit gradient (null for a solve): adj_g in
+    // omp's layout holds g_ij of the free pairs (NaN elsewhere); adj_gd and
+    // adj_hd, one per row like omdp, hold g_ii and S_ii + 1 / omega_ii^2.
+    const T *adj_g;
+    const T *adj_gd;
+    const T *adj_hd;
 };
 
 // Column slice b of Gc over p columns: [slice_lo(b), slice_lo(b + 1)).
