@@ -40,17 +40,6 @@ def free_coordinates(omega):
     return coords
 
 
-def _unit(c, p):
-    """The symmetric change of Omega that moves coordinate c by one."""
-    E = np.zeros((p, p))
-    if c[0] == "d":
-        E[c[1], c[1]] = 1.0
-    else:
-        E[c[1], c[2]] = 1.0
-        E[c[2], c[1]] = 1.0
-    return E
-
-
 def residuals(S, omega, lam: float, coords=None) -> np.ndarray:
     """The stationarity residuals R_r at Omega, in the order of coords."""
     S, om = _f64(S), _f64(omega)
@@ -67,23 +56,36 @@ def residuals(S, omega, lam: float, coords=None) -> np.ndarray:
     return out
 
 
+def _unit_times_S(c, S):
+    """E_c S: E_c has ones at (k, l) and (l, k) (at (k, k) for a diagonal
+    coordinate), so row k of E_c S is S_l., row l is S_k., the rest is 0."""
+    dW = np.zeros_like(S)
+    if c[0] == "d":
+        dW[c[1]] = S[c[1]]
+    else:
+        dW[c[1]] += S[c[2]]
+        dW[c[2]] += S[c[1]]
+    return dW
+
+
 def jacobian(S, omega, coords=None) -> np.ndarray:
     """J[r, t] = dR_r / dtheta_t.  Moving theta_t by one changes W by E_t S
     and, for a diagonal coordinate, 1/omega_ii by -1/omega_ii^2."""
     S, om = _f64(S), _f64(omega)
-    p = S.shape[0]
     coords = free_coordinates(om) if coords is None else coords
     N = len(coords)
+    # residual r reads W at (ri, rj) and (rj, ri); a diagonal one has ri = rj
+    # and counts the entry once
+    ri = np.array([c[1] for c in coords])
+    rj = np.array([c[1] if c[0] == "d" else c[2] for c in coords])
+    isd = np.array([c[0] == "d" for c in coords])
     J = np.zeros((N, N))
     for t, ct in enumerate(coords):
-        dW = _unit(ct, p) @ S
-        for r, c in enumerate(coords):
-            if c[0] == "d":
-                i = c[1]
-                J[r, t] = dW[i, i] + (1.0 / om[i, i] ** 2 if ct == c else 0.0)
-            else:
-                i, j = c[1], c[2]
-                J[r, t] = dW[i, j] + dW[j, i]
+        dW = _unit_times_S(ct, S)
+        col = dW[ri, rj] + np.where(isd, 0.0, dW[rj, ri])
+        if ct[0] == "d":
+            col[t] += 1.0 / om[ct[1], ct[1]] ** 2
+        J[:, t] = col
     return J
 
 
