@@ -16,7 +16,18 @@ two rows of W: read S row, read and write W row, twice) and N_diag the
 diagonals that moved (one row each).
 
 Also printed: the sweep kernel's own bandwidth (event-timed, `roofline`) and
-the CPU oracle timed on a bounded sample of the same problem (`cpu_baseline`).
+the CPU oracle timed on a bounded sample of the same problem (`cpu_baseline`),
+and two side measurements on their own workloads:
+
+* `batched`: 64 independent Erdos-Renyi problems, p ~ U[200, 3000], n = p/2,
+  each on a 16-value lambda path 0.5 -> 0.05 with warm starts, FP32, tol 1e-5,
+  in one persistent launch (concord_fit_batched); solves/s against a loop of
+  plain single-solve fits along the same paths at the same tolerance (timed on
+  every 4th problem by size and extrapolated over all 64 by linear
+  interpolation in p, unless --plain-all times all of them).
+* `backward`: the implicit gradient (concord_backward) at p = 2000, n = 1000,
+  chain Omega_0, lambda = 0.15, L = |Omega-hat - Omega_0|_F^2, FP64, against the
+  forward solve at the same tolerance.
 """
 from __future__ import annotations
 
@@ -88,6 +99,119 @@ def measured_traffic(p: int, n: int, lam: float, dtype: str):
     return float(rec["bytes_per_launch"])
 
 
+def batched_measurement(plain_all: bool) -> dict:
+    """Config-4 batch in one launch against the plain single-solve loop."""
+    import warnings
+
+    import numpy as np
+    import torch
+
+    from paper_2106_09382_amd import _lib, datagen
+
+    t0 = time.perf_counter()
+    probs = datagen.batched_problems(0)
+    lams = [float(x) for x in datagen.lambda_path()]
+    log(f"bench: batched workload ready in {time.perf_counter() - t0:.1f} s")
+    Xs = [torch.tensor(q["y"], dtype=torch.float32, device="cuda") for q in probs]
+    ps = np.array([q["p"] for q in probs])
+    tol, maxit = 1e-5, 500
+    B, L = len(probs), len(lams)
+
+    def run_batch():
+        with warnings.catch_warnings():
+            warnings.simplefilter("ignore")
+            return _lib.fit_batched(Xs, lams, tol, maxit, kind="Y", check=False)
+
+    run_batch()  # warm-up (also allocates the outputs once)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    outs, infos, code = run_batch()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    sweeps = sum(i["sweeps"] for row in infos for i in row)
+    moved = np.array([sum(i["moved_pairs"] for i in row) for row in infos], dtype=float)
+    mdiag = np.array([sum(i["moved_diag"] for i in row) for row in infos], dtype=float)
+    sw = np.array([sum(i["sweeps"] for i in row) for row in infos], dtype=float)
+    m = ps + (ps & 1) - 1
+    byt = float((4.0 * (1.5 * ps * m * sw + 6.0 * ps * moved + 3.0 * ps * mdiag)).sum())
+    log(f"bench: batched {B} x {L} solves in {wall:.2f} s (code {code})")
+
+    order = np.argsort(ps)
+    subset = list(range(B)) if plain_all else [int(b) for b in order[::4]]
+    times = {}
+    for b in subset:
+        om = None
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        with warnings.catch_warnings():
+            warnings.simplefilter("ignore")
+            for lam in lams:
+                om, _ = _lib.fit(Xs[b], lam, tol, maxit, kind="Y", omega0=om, check=False)
+        torch.cuda.synchronize()
+        times[b] = time.perf_counter() - t1
+    if plain_all:
+        plain_total = sum(times.values())
+        how = "measured on all 64 problems"
+    else:
+        xp = np.array([ps[b] for b in subset], dtype=float)
+        fp = np.array([times[b] for b in subset])
+        plain_total = float(np.interp(ps.astype(float), xp, fp).sum())
+        how = (f"measured on {len(subset)} problems (every 4th by p, "
+               f"{sum(times.values()):.1f} s), linearly interpolated in p over all 64")
+    log(f"bench: plain loop {plain_total:.1f} s ({how})")
+    return {
+        "workload": ("64 ER problems p~U[200,3000] (seed 4000), n=p/2, 16-value lambda path "
+                     "0.5->0.05 with warm starts, FP32, tol 1e-5, maxit 500 per lambda, from Y"),
+        "solves": B * L,
+        "wall_s": wall,
+        "solves_per_s": B * L / wall,
+        "plain_loop_s": plain_total,
+        "plain_solves_per_s": B * L / plain_total,
+        "speedup_vs_plain": plain_total / wall,
+        "plain_loop_how": how,
+        "status": code,
+        "sweeps_total": int(sweeps),
+        "algorithmic_GBs": byt / wall / 1e9,
+        "workgroups": int(sum(row[0]["row_groups"] for row in infos)),
+    }
+
+
+def backward_measurement() -> dict:
+    """Config-5 implicit gradient against its forward solve."""
+    import numpy as np
+    import torch
+
+    from paper_2106_09382_amd import _lib, datagen
+
+    pr = datagen.problem(5)
+    S = _lib.gram(torch.tensor(pr["y"], device="cuda"))
+    O0 = torch.tensor(pr["omega0"], device="cuda")
+    tol, maxit = pr["tol"], 5000
+    fw, bw = [], []
+    for rep in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        om, fi = _lib.fit(S, pr["lam"], tol, maxit)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        gS, gl, bi = _lib.backward(S, om, 2.0 * (om - O0), tol, maxit)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        if rep:
+            fw.append(t1 - t0)
+            bw.append(t2 - t1)
+    return {
+        "workload": "p=2000 n=1000 chain Omega_0, lambda=0.15, L=|Omega-hat - Omega_0|_F^2, FP64, tol 1e-8",
+        "forward_ms": 1e3 * float(np.mean(fw)),
+        "backward_ms": 1e3 * float(np.mean(bw)),
+        "backward_over_forward": float(np.mean(bw) / np.mean(fw)),
+        "forward_sweeps": fi["sweeps"],
+        "backward_sweeps": bi["sweeps"],
+        "nnz_upper": fi["nnz_upper"],
+        "grad_lambda": gl,
+    }
+
+
 def _cpu_model() -> str:
     try:
         for line in open("/proc/cpuinfo"):
@@ -114,6 +238,10 @@ def main() -> int:
     ap.add_argument("--threads", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched measurement")
+    ap.add_argument("--no-backward", action="store_true", help="skip the backward measurement")
+    ap.add_argument("--plain-all", action="store_true",
+                    help="time the plain single-solve loop on all 64 batched problems")
     ap.add_argument("--dump-y", metavar="PATH",
                     help="write the workload's Y (raw float64, n x p) to PATH and exit; "
                          "input for the native driver concord_bench")
@@ -224,6 +352,10 @@ def main() -> int:
         log(f"bench: timing the CPU oracle on a ~{args.cpu_seconds:.0f} s sample")
         res["cpu_baseline"] = cpu_oracle_baseline(y, args.p, args.lam, elem, sweeps,
                                                   bytes_launch / max(sweeps, 1), args.cpu_seconds)
+    if not args.no_batched:
+        res["batched"] = batched_measurement(args.plain_all)
+    if not args.no_backward:
+        res["backward"] = backward_measurement()
     print(json.dumps(res), flush=True)
     return 0
 
