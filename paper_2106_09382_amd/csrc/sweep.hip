@@ -467,18 +467,6 @@ __device__ void pcd_solve(const SweepParams<T> &P, int g, int G, unsigned char *
                         if (e < x.n)
                             vpre = fma(pdl[k * D + e], x.sv[e], vpre);
                 }
-                if (flushed[u]) {
-                    np[k] = 0;
-                    flushed[u] = false;
-                }
-                const int n0 = np[k];
-                if (x.pubd) {
-                    // once per sweep: W_ii with the pending updates, loaded here
-                    vdpre = WLDS ? wblk[(size_t)k * nc + (i - c0)] : Wg[(size_t)i * p + i];
-                    for (int e = 0; e < n0; ++e)
-                        vdpre = fma(pdl[k * D + e], S[(size_t)pj[k * D + e] * p + i], vdpre);
-                }
-
                 // ---- wait for the published numerator entries of this colour
                 U blo = 0, bhi = 0, bd = 0;
                 {
@@ -514,6 +502,21 @@ __device__ void pcd_solve(const SweepParams<T> &P, int g, int G, unsigned char *
                 if (lfail) {
                     *s_fail = 1;
                     continue;
+                }
+
+                // ---- a row rewritten last step starts a new pending list.  The
+                // once-per-sweep W_ii read comes after the wait: a load issued
+                // before the poll would hold up the poll's first answer (a
+                // wave's loads complete in order).
+                if (flushed[u]) {
+                    np[k] = 0;
+                    flushed[u] = false;
+                }
+                const int n0 = np[k];
+                if (x.pubd) {
+                    vdpre = WLDS ? wblk[(size_t)k * nc + (i - c0)] : Wg[(size_t)i * p + i];
+                    for (int e = 0; e < n0; ++e)
+                        vdpre = fma(pdl[k * D + e], S[(size_t)pj[k * D + e] * p + i], vdpre);
                 }
 
                 // ---- eq. (3) for the pair, eq. (2) after the last colour
