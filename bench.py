@@ -21,7 +21,9 @@ and two side measurements on their own workloads:
 
 * `batched`: 64 independent Erdos-Renyi problems, p ~ U[200, 3000], n = p/2,
   each on a 16-value lambda path 0.5 -> 0.05 with warm starts, FP32, tol 1e-5,
-  in one persistent launch (concord_fit_batched); solves/s against a loop of
+  in one persistent launch (concord_fit_batched), timed once with the built-in
+  workgroup plan and once with the plan the autotuner builds from that run's
+  per-problem device times (the reported rate); solves/s against a loop of
   plain single-solve fits along the same paths at the same tolerance (timed on
   every 4th problem by size and extrapolated over all 64 by linear
   interpolation in p, unless --plain-all times all of them).
@@ -117,17 +119,23 @@ def batched_measurement(plain_all: bool) -> dict:
     tol, maxit = 1e-5, 500
     B, L = len(probs), len(lams)
 
-    def run_batch():
+    from paper_2106_09382_amd import autotune
+
+    def run_batch(pw=None):
         with warnings.catch_warnings():
             warnings.simplefilter("ignore")
-            return _lib.fit_batched(Xs, lams, tol, maxit, kind="Y", check=False)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = _lib.fit_batched(Xs, lams, tol, maxit, kind="Y", check=False,
+                                   problem_workgroups=pw)
+            torch.cuda.synchronize()
+            return res, time.perf_counter() - t0
 
-    run_batch()  # warm-up (also allocates the outputs once)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    outs, infos, code = run_batch()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    (outs, infos0, code0), wall_default = run_batch()
+    log(f"bench: batched with the built-in plan: {wall_default:.2f} s")
+    total = int(sum(row[0]["row_groups"] for row in infos0))
+    tuned = autotune.plan_from_infos([int(x) for x in ps], infos0, total)
+    (outs, infos, code), wall = run_batch(tuned)
     sweeps = sum(i["sweeps"] for row in infos for i in row)
     moved = np.array([sum(i["moved_pairs"] for i in row) for row in infos], dtype=float)
     mdiag = np.array([sum(i["moved_diag"] for i in row) for row in infos], dtype=float)
@@ -164,6 +172,8 @@ def batched_measurement(plain_all: bool) -> dict:
                      "0.5->0.05 with warm starts, FP32, tol 1e-5, maxit 500 per lambda, from Y"),
         "solves": B * L,
         "wall_s": wall,
+        "wall_s_builtin_plan": wall_default,
+        "plan": "autotuned from the built-in-plan run's per-problem device times",
         "solves_per_s": B * L / wall,
         "plain_loop_s": plain_total,
         "plain_solves_per_s": B * L / plain_total,

@@ -566,7 +566,7 @@ bool plan_workgroups(const std::vector<int> &ps, int total, int threads, std::ve
         int best = -1;
         double bc = -1.0;
         for (int b = 0; b < B; ++b) {
-            if ((*G)[b] * 8 > ps[b])  // keep >= 8 rows per workgroup
+            if (((*G)[b] + 1) * 8 > ps[b])  // keep >= 8 rows per workgroup
                 continue;
             const double c = w[b] / (*G)[b];
             if (c > bc) {

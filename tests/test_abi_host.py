@@ -121,3 +121,17 @@ def test_batched_invalid_arguments_return_einval(lib):
     assert _fit_batched(lib, maxit=0) == -1
     assert _fit_batched(lib, L=3, maxit=(1 << 23)) == -1  # L * maxit > 2^24
     assert _fit_batched(lib, dt=5) == -1
+
+
+def test_autotune_plan_deals_by_work():
+    from paper_2106_09382_amd import autotune
+    ps = [200, 1500, 3000, 50]
+    G = autotune.plan(ps, [1.0, 1.0, 1.0, 1.0], 40)
+    assert sum(G) <= 40 and all(g >= autotune.min_workgroups(p) for g, p in zip(G, ps))
+    assert all(g * 8 <= p or g == autotune.min_workgroups(p) for g, p in zip(G, ps))
+    heavy = autotune.plan(ps, [1.0, 10.0, 1.0, 1.0], 40)
+    assert heavy[1] > G[1]
+    infos = [[{"sweep_ms": 5.0, "row_groups": g}] for g in G]
+    assert sum(autotune.plan_from_infos(ps, infos, 40)) <= 40
+    with pytest.raises(ValueError):
+        autotune.plan([5000] * 10, [1.0] * 10, 12)

@@ -238,3 +238,22 @@ def test_config4_full_batch_properties(lib):
             # most 2 tol |S|_1 per entry, plus FP32 rounding of Omega
             bound = 4e-5 * row1 * max(1.0, np.abs(om).max()) + 1e-4
             assert r["support"] < bound and r["zeros"] < bound and r["diag"] < bound, (b, l, r)
+
+
+def test_explicit_and_autotuned_plans_give_the_same_bits(lib):
+    from paper_2106_09382_amd import autotune
+    probs = _small_batch()
+    ps = [pr["p"] for pr in probs]
+    ref, infos, rcode = _run(lib, [pr["S"] for pr in probs], LAMS, TOL, MAXIT)
+    tuned = autotune.plan_from_infos(ps, infos, 64)
+    got, infos2, code = _run(lib, [pr["S"] for pr in probs], LAMS, TOL, MAXIT,
+                             problem_workgroups=tuned)
+    assert code == rcode
+    assert [row[0]["row_groups"] for row in infos2] == tuned
+    for b in range(len(probs)):
+        for l in range(len(LAMS)):
+            assert np.array_equal(got[b][l], ref[b][l]), (b, l)
+    # a count below a problem's minimum is rejected before any device work
+    _, _, bad = _run(lib, [pr["S"] for pr in probs], LAMS, TOL, MAXIT,
+                     problem_workgroups=[0] * len(ps))
+    assert bad == -1
