@@ -27,6 +27,14 @@ and two side measurements on their own workloads:
   plain single-solve fits along the same paths at the same tolerance (timed on
   every 4th problem by size and extrapolated over all 64 by linear
   interpolation in p, unless --plain-all times all of them).
+* `floor`: the sweep's two floors.  Bandwidth: B_sweep / 8 TB/s.  Sync: m
+  dependent colour steps x the cost of one step with nothing to move, measured
+  as a solve at lambda = 1000 lambda_max-scale (no pair ever moves; two sweeps
+  of pure dependency chain, same launch shape).  T_floor = max of the two per
+  sweep, `frac` = T_floor / t_sweep, `binds` names the larger.
+* `fp32`: the same solve in FP32 (S 100 MB + W 100 MB, the cache-resident
+  regime), with a cache-resident copy bandwidth (a 64 MiB device copy,
+  repeated) beside the HBM peak.
 * `backward`: the implicit gradient (concord_backward) at p = 2000, n = 1000,
   chain Omega_0, lambda = 0.15, L = |Omega-hat - Omega_0|_F^2, FP64, against the
   forward solve at the same tolerance.
@@ -183,6 +191,78 @@ def batched_measurement(plain_all: bool) -> dict:
         "sweeps_total": int(sweeps),
         "algorithmic_GBs": byt / wall / 1e9,
         "workgroups": int(sum(row[0]["row_groups"] for row in infos)),
+    }
+
+
+def floor_measurement(Y, shape: dict, bytes_per_sweep: float, t_sweep_ms: float, m: int) -> dict:
+    """Bandwidth and synchronisation floors of one sweep (see the module doc)."""
+    import torch
+
+    from paper_2106_09382_amd import _lib
+
+    ts = []
+    for _ in range(3):
+        _, info = _lib.fit(Y, 1000.0, 1e-6, 10, kind="Y", check=False, **shape)
+        torch.cuda.synchronize()
+        ts.append(info["sweep_ms"] * 1e3 / (max(info["sweeps"], 1) * m))
+    t_step = float(min(ts))
+    t_bw = bytes_per_sweep / (HBM_PEAK_GBS * 1e9) * 1e3
+    t_sync = t_step * m / 1e3
+    t_floor = max(t_bw, t_sync)
+    return {
+        "us_per_step_no_moves": t_step,
+        "sweeps_no_moves": info["sweeps"],
+        "t_bandwidth_ms": t_bw,
+        "t_sync_ms": t_sync,
+        "t_floor_ms": t_floor,
+        "t_sweep_ms": t_sweep_ms,
+        "frac": t_floor / t_sweep_ms,
+        "binds": "sync" if t_sync >= t_bw else "bandwidth",
+    }
+
+
+def fp32_measurement(Y, lam: float, tol: float, shape: dict) -> dict:
+    """The benchmark solve in FP32 and a cache-resident copy bandwidth."""
+    import numpy as np
+    import torch
+
+    from paper_2106_09382_amd import _lib
+
+    Y32 = Y.float()
+    p = Y.shape[1]
+    m = p + (p & 1) - 1
+    infos = []
+    for _ in range(3):
+        _, info = _lib.fit(Y32, lam, tol, 500, kind="Y", check=False, **shape)
+        torch.cuda.synchronize()
+        infos.append(info)
+    last = infos[-1]
+    byt = sweep_bytes(p, 4, last["sweeps"], last["moved_pairs"], last["moved_diag"])
+    t = float(np.mean([i["sweep_ms"] for i in infos[1:]]))
+    # cache-resident copy: 64 MiB in, 64 MiB out, repeated
+    a = torch.empty(16 << 20, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    reps = 50
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2 * a.numel() * 4 * reps / (e0.elapsed_time(e1) / 1e3) / 1e9
+    return {
+        "sweep_kernel_ms": t,
+        "sweeps": last["sweeps"],
+        "code": last["code"],
+        "tol_eff": last["tol_eff"],
+        "algorithmic_GBs": byt / (t / 1e3) / 1e9,
+        "us_per_colour_step": t * 1e3 / max(last["sweeps"] * m, 1),
+        "cache_copy_GBs": copy_gbs,
+        "frac_of_cache_copy": byt / (t / 1e3) / 1e9 / copy_gbs,
     }
 
 
@@ -362,6 +442,10 @@ def main() -> int:
         log(f"bench: timing the CPU oracle on a ~{args.cpu_seconds:.0f} s sample")
         res["cpu_baseline"] = cpu_oracle_baseline(y, args.p, args.lam, elem, sweeps,
                                                   bytes_launch / max(sweeps, 1), args.cpu_seconds)
+    if args.p == 5000 and args.dtype == "f64":
+        res["floor"] = floor_measurement(Y, shape, bytes_launch / max(sweeps, 1),
+                                         float(np.mean(sweep_ms)) / max(sweeps, 1), m)
+        res["fp32"] = fp32_measurement(Y, args.lam, args.tol, shape)
     if not args.no_batched:
         res["batched"] = batched_measurement(args.plain_all)
     if not args.no_backward:
