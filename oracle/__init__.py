@@ -16,6 +16,8 @@ write them).  The helpers here are plain NumPy definitions:
   omega_ii (S Omega)_ii = 1, G_ij + lam sign(omega_ij) = 0 where omega_ij != 0,
   and |G_ij| <= lam where omega_ij = 0.
 
+``oracle.active`` holds the active-set scheme (greedy edge colouring of the
+support, sweeps over it, full sweeps to decide convergence).
 ``oracle.backward`` holds the implicit gradient of the estimate (dL/dS and
 dL/dlam from the stationarity system on the active set, by a dense solve).
 """
@@ -58,6 +60,10 @@ def _load():
     lib.oracle_cd.argtypes = [dp, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int,
                               dp, dp, dp, dp]
     lib.oracle_cd.restype = ctypes.c_int
+    ip = ctypes.POINTER(ctypes.c_int32)
+    lib.oracle_pcd_colouring.argtypes = [dp, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                         ctypes.c_int, dp, dp, ip, ip, ctypes.c_int, dp, dp]
+    lib.oracle_pcd_colouring.restype = ctypes.c_int
     lib.oracle_offdiag_update.argtypes = [dp, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                           ctypes.c_double]
     lib.oracle_offdiag_update.restype = ctypes.c_double
@@ -114,6 +120,32 @@ def pcd(S, lam: float, tol: float, maxit: int, omega0=None, colour_limit: int = 
                             int(colour_limit), int(bool(serial)), _dp(tr), _dp(info))
     if rc:
         raise OracleError(f"oracle_pcd returned {rc}")
+    inf = _info(info)
+    return om, inf, tr[: inf["sweeps"]].copy()
+
+
+def pcd_colouring(S, lam: float, tol: float, maxit: int, classes, omega0=None):
+    """CONCORD-PCD over a given edge colouring (a list of colour classes, each
+    a list of 0-based pairs (i, j) forming a matching).  Returns (Omega, info,
+    delta_trace)."""
+    S = _f64(S)
+    p = S.shape[0]
+    flat = [x for cls in classes for pr in cls for x in pr]
+    starts = [0]
+    for cls in classes:
+        starts.append(starts[-1] + len(cls))
+    pairs = np.ascontiguousarray(np.array(flat if flat else [0], dtype=np.int32))
+    cst = np.ascontiguousarray(np.array(starts, dtype=np.int32))
+    om = np.empty((p, p))
+    tr = np.zeros(maxit)
+    info = np.zeros(5)
+    o0 = None if omega0 is None else _f64(omega0)
+    ip = ctypes.POINTER(ctypes.c_int32)
+    rc = _load().oracle_pcd_colouring(_dp(S), p, float(lam), float(tol), int(maxit), _dp(o0),
+                                      _dp(om), pairs.ctypes.data_as(ip), cst.ctypes.data_as(ip),
+                                      len(classes), _dp(tr), _dp(info))
+    if rc:
+        raise OracleError(f"oracle_pcd_colouring returned {rc}")
     inf = _info(info)
     return om, inf, tr[: inf["sweeps"]].copy()
 

@@ -269,6 +269,84 @@ int oracle_pcd(const double *S, int p, double lam, double tol, int maxit,
 }
 
 /*
+ * CONCORD-PCD over a given edge colouring (Section 4: the construction of
+ * Theorem 2's update order extends to any edge colouring).  Colour c holds
+ * the pairs pairs[2 e], pairs[2 e + 1] for e in [colour_start[c],
+ * colour_start[c + 1]), 0-based, each colour a matching.  A sweep updates the
+ * pairs of colour 0, 1, ..., ncol - 1 in that order, all pairs of a colour
+ * from the same Omega (Lemma 2), then the diagonal step.  Pairs in no colour
+ * keep their value.  delta, stopping rule, info and return codes as for
+ * oracle_pcd (info[4] counts colour steps).
+ */
+int oracle_pcd_colouring(const double *S, int p, double lam, double tol, int maxit,
+                         const double *omega0, double *omega, const int32_t *pairs,
+                         const int32_t *colour_start, int ncol, double *delta_trace,
+                         double *info)
+{
+    int rc = check_inputs(S, p, lam, tol, maxit);
+    if (rc)
+        return rc;
+    if (ncol < 0 || (ncol > 0 && (!pairs || !colour_start)))
+        return -1;
+    int widest = 0;
+    for (int c = 0; c < ncol; ++c) {
+        int w = colour_start[c + 1] - colour_start[c];
+        if (w < 0)
+            return -1;
+        if (w > widest)
+            widest = w;
+    }
+    double *nv = (double *)malloc(sizeof(double) * (widest + 1));
+    double *od = (double *)malloc(sizeof(double) * p);
+    start_point(omega, omega0, p);
+    int t = 0, converged = 0;
+    double delta = 0.0;
+    long long steps = 0;
+    while (t < maxit) {
+        ++t;
+        delta = 0.0;
+        for (int c = 0; c < ncol; ++c) {
+            int e0 = colour_start[c], e1 = colour_start[c + 1];
+            for (int e = e0; e < e1; ++e)
+                nv[e - e0] = offdiag_new(S, omega, p, pairs[2 * e], pairs[2 * e + 1], lam);
+            for (int e = e0; e < e1; ++e) {
+                int a = pairs[2 * e], b = pairs[2 * e + 1];
+                double d = fabs(nv[e - e0] - omega[(size_t)a * p + b]);
+                if (d > delta)
+                    delta = d;
+                omega[(size_t)a * p + b] = nv[e - e0];
+                omega[(size_t)b * p + a] = nv[e - e0];
+            }
+            ++steps;
+        }
+        for (int i = 0; i < p; ++i)
+            od[i] = diag_new(S, omega, p, i);
+        for (int i = 0; i < p; ++i) {
+            double d = fabs(od[i] - omega[(size_t)i * p + i]);
+            if (d > delta)
+                delta = d;
+            omega[(size_t)i * p + i] = od[i];
+        }
+        if (delta_trace)
+            delta_trace[t - 1] = delta;
+        if (delta < tol) {
+            converged = 1;
+            break;
+        }
+    }
+    if (info) {
+        info[0] = t;
+        info[1] = delta;
+        info[2] = converged;
+        info[3] = (double)count_upper(omega, p);
+        info[4] = (double)steps;
+    }
+    free(nv);
+    free(od);
+    return 0;
+}
+
+/*
  * CONCORD-CD (Section 2.1): each sweep updates the p diagonals by eq. (2),
  * then the p(p-1)/2 off-diagonals by eq. (3) in lexicographic order
  * (1,2), (1,3), ..., (p-1,p); every update uses the latest values.
