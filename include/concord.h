@@ -68,7 +68,7 @@ typedef struct {
     int32_t w_in_lds;   /*   1 if W blocks were held in LDS */
     int32_t block_threads;
     int32_t pending_depth; /* row updates held back before a row of W is rewritten */
-    int32_t reserved;
+    int32_t active_sweeps; /* active-set mode: sweeps over the support's colouring */
 } concord_info;
 
 /* Launch/tuning options; zero-initialise for defaults. */
@@ -90,6 +90,14 @@ typedef struct {
     /* Optional device p x p array (element type dt): receives the maintained
      * product W = Omega S as the solve leaves it (for checks). */
     void *w_out;
+    /* Active-set sweeps (the construction of Theorem 2 with another edge
+     * colouring, Section 4): 1 = after each full sweep of Algorithm 1 that has
+     * not converged, colour the support of Omega greedily and sweep over
+     * those colours (then the diagonal) until their delta < tol or
+     * active_maxit sweeps (0 = 20 maxit); only full sweeps decide convergence
+     * and count in info->sweeps and maxit.  0 = plain Algorithm 1. */
+    int32_t active_set;
+    int32_t active_maxit;
 } concord_options;
 
 /*

@@ -40,7 +40,7 @@ class ConcordInfo(ctypes.Structure):
         ("w_in_lds", ctypes.c_int32),
         ("block_threads", ctypes.c_int32),
         ("pending_depth", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("active_sweeps", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:
@@ -59,6 +59,8 @@ class ConcordOptions(ctypes.Structure):
         ("timestamp_steps", ctypes.c_int32),
         ("reserved", ctypes.c_int32),
         ("w_out", ctypes.c_void_p),
+        ("active_set", ctypes.c_int32),
+        ("active_maxit", ctypes.c_int32),
     ]
 
 
@@ -162,7 +164,8 @@ def fit(X: torch.Tensor, lam: float, tol: float = 1e-6, maxit: int = 500, *, kin
         omega0: torch.Tensor | None = None, out: torch.Tensor | None = None, stream=None,
         row_groups: int = 0, col_slices: int = 0, block_threads: int = 0, w_in_lds: int = 0,
         pending_depth: int = 0, trace: bool = False, check: bool = True,
-        timestamps: torch.Tensor | None = None, w_out: torch.Tensor | None = None):
+        timestamps: torch.Tensor | None = None, w_out: torch.Tensor | None = None,
+        active_set: bool = False, active_maxit: int = 0):
     """One CONCORD-PCD solve.  X is S (p x p) or, with kind='Y', Y (n x p).
 
     Returns (omega, info dict); info['delta_trace'] holds every sweep's delta
@@ -195,7 +198,7 @@ def fit(X: torch.Tensor, lam: float, tol: float = 1e-6, maxit: int = 500, *, kin
         o0 = ctypes.c_void_p(omega0.data_ptr())
     info = ConcordInfo()
     opts = ConcordOptions(row_groups, col_slices, block_threads, w_in_lds, pending_depth, None,
-                          None, 0, 0, None)
+                          None, 0, 0, None, int(bool(active_set)), int(active_maxit))
     if w_out is not None:
         _check_dev(w_out, "w_out")
         if w_out.dtype != X.dtype or tuple(w_out.shape) != (p, p):

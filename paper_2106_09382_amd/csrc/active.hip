@@ -1,0 +1,99 @@
+// Support kernels of the active-set sweeps: the support of the current Omega
+// as an edge list (to be coloured) and the dense Omega back from the sweep
+// layout of a colour table.
+#include "device_common.hpp"
+#include "support.hpp"
+
+namespace concord {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+inline int grid_for(long long work, int cap = 4096)
+{
+    long long g = (work + kThreads - 1) / kThreads;
+    if (g < 1)
+        g = 1;
+    return (int)(g > cap ? cap : g);
+}
+
+// Pairs i < j with omega_ij != 0, appended to edges[2 e], edges[2 e + 1]
+// (order unspecified; *count ends as the number found, even past cap).
+template <typename T>
+__global__ void support_edges_kernel(const T *__restrict__ omega, int p, int *__restrict__ count,
+                                     int *__restrict__ edges, long long cap)
+{
+    const long long total = (long long)p * p;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+         e += (long long)gridDim.x * blockDim.x) {
+        const int i = (int)(e / p), j = (int)(e - (long long)i * p);
+        if (j > i && omega[e] != T(0)) {
+            const int slot = atomicAdd(count, 1);
+            if (slot < cap) {
+                edges[2 * (long long)slot] = i;
+                edges[2 * (long long)slot + 1] = j;
+            }
+        }
+    }
+}
+
+// Dense Omega from the copies of column slice 0: omega_ij at colour r of
+// row i's table entry, omega_ii per row.  Entries in no colour stay 0.
+template <typename T>
+__global__ void scatter_omega_kernel(const T *__restrict__ omp, const T *__restrict__ omdp,
+                                     const int *__restrict__ part, int mt, int Gr, int Gc, int NR,
+                                     int p, T *__restrict__ omega)
+{
+    const long long total = (long long)Gr * (mt + 1) * NR;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+         e += (long long)gridDim.x * blockDim.x) {
+        const long long per = (long long)(mt + 1) * NR;
+        const int a = (int)(e / per);
+        const long long rem = e - (long long)a * per;
+        const int r = (int)(rem / NR), k = (int)(rem - (long long)r * NR);
+        const int i = a + k * Gr;
+        if (i >= p)
+            continue;
+        const int g = a * Gc;
+        if (r == mt) {
+            omega[(size_t)i * p + i] = omdp[(size_t)g * NR + k];
+        } else {
+            const int j = part[(size_t)r * p + i];
+            if (j >= 0)
+                omega[(size_t)i * p + j] = omp[((size_t)g * mt + r) * NR + k];
+        }
+    }
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_support_edges(const T *omega, int p, int *count, int *edges, long long cap,
+                                hipStream_t st)
+{
+    hipLaunchKernelGGL(support_edges_kernel<T>, dim3(grid_for((long long)p * p, 4096)),
+                       dim3(kThreads), 0, st, omega, p, count, edges, cap);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_scatter_omega(const T *omp, const T *omdp, const int *part, int mt, int Gr,
+                                int Gc, int NR, int p, T *omega, hipStream_t st)
+{
+    hipLaunchKernelGGL(scatter_omega_kernel<T>,
+                       dim3(grid_for((long long)Gr * (mt + 1) * NR, 4096)), dim3(kThreads), 0, st,
+                       omp, omdp, part, mt, Gr, Gc, NR, p, omega);
+    return hipGetLastError();
+}
+
+#define CONCORD_ACTIVE_INST(T)                                                                   \
+    template hipError_t launch_support_edges<T>(const T *, int, int *, int *, long long,        \
+                                                hipStream_t);                                    \
+    template hipError_t launch_scatter_omega<T>(const T *, const T *, const int *, int, int, int, \
+                                                int, int, T *, hipStream_t);
+
+CONCORD_ACTIVE_INST(float)
+CONCORD_ACTIVE_INST(double)
+
+}  // namespace concord

@@ -160,6 +160,50 @@ int map_hip(hipError_t e)
             return map_hip(e_);              \
     } while (0)
 
+// Greedy edge colouring of the support (edges i < j, in any order): edges in
+// lexicographic order each take the smallest colour neither endpoint has
+// used.  Writes the m x p partner table (part[c * p + i] = partner of i in
+// colour c, -1 idle) and returns m, padded to at least 2 colours (the sweep
+// kernel's last colour publishes for the first).
+int greedy_colouring(const int *edges, int ne, int p, std::vector<int> *part)
+{
+    std::vector<std::pair<int, int>> E((size_t)ne);
+    for (int e = 0; e < ne; ++e)
+        E[e] = {std::min(edges[2 * e], edges[2 * e + 1]), std::max(edges[2 * e], edges[2 * e + 1])};
+    std::sort(E.begin(), E.end());
+    std::vector<std::vector<uint64_t>> used((size_t)p);
+    std::vector<int> colour((size_t)ne);
+    int m = 0;
+    for (int e = 0; e < ne; ++e) {
+        std::vector<uint64_t> &ui = used[E[e].first], &uj = used[E[e].second];
+        int c = 0;
+        for (size_t w = 0;; ++w) {
+            const uint64_t a = w < ui.size() ? ui[w] : 0, b = w < uj.size() ? uj[w] : 0;
+            const uint64_t freeb = ~(a | b);
+            if (freeb) {
+                c = (int)(64 * w) + __builtin_ctzll(freeb);
+                break;
+            }
+        }
+        const size_t w = (size_t)c / 64;
+        if (ui.size() <= w)
+            ui.resize(w + 1, 0);
+        if (uj.size() <= w)
+            uj.resize(w + 1, 0);
+        ui[w] |= 1ull << (c % 64);
+        uj[w] |= 1ull << (c % 64);
+        colour[e] = c;
+        m = std::max(m, c + 1);
+    }
+    m = std::max(m, 2);
+    part->assign((size_t)m * p, -1);
+    for (int e = 0; e < ne; ++e) {
+        (*part)[(size_t)colour[e] * p + E[e].first] = E[e].second;
+        (*part)[(size_t)colour[e] * p + E[e].second] = E[e].first;
+    }
+    return m;
+}
+
 template <typename T>
 int fit_impl(concord_input kind, const void *X, int64_t n64, int64_t p64, double lambda,
              double tol, int32_t maxit, const void *omega0, void *omega, concord_info *info,
@@ -194,16 +238,26 @@ int fit_impl(concord_input kind, const void *X, int64_t n64, int64_t p64, double
     const size_t pp = (size_t)p * p;
     const size_t oS = (kind == CONCORD_INPUT_Y) ? cv.take<T>(pp) : 0;
     const size_t oW = cv.take<T>(pp);
-    const size_t oOmp = cv.take<T>((size_t)G * C.m * sh.nr_max);
+    // Active-set sweeps colour the support greedily: at most 2 Delta - 1 <
+    // 2 p colours, so the sweep layout is sized for that many.
+    const bool active = opts && opts->active_set;
+    const int amax = active ? (opts->active_maxit > 0 ? opts->active_maxit : 20 * maxit) : 0;
+    const int Mmax = active ? std::max(C.m, 2 * p) : C.m;
+    const long long ecap = active ? (long long)p * (p - 1) / 2 : 0;
+    const size_t oOmp = cv.take<T>((size_t)G * Mmax * sh.nr_max);
     const size_t oOmdp = cv.take<T>((size_t)G * sh.nr_max);
     const size_t oSd = cv.take<T>(p);
     const size_t PS = (size_t)sh.Gr * sh.nr_max;  // published slots per colour
-    const size_t oPc = cv.take<T>(2 * (size_t)C.m * PS);
+    const size_t oPc = cv.take<T>(2 * (size_t)Mmax * PS);
     const size_t oPd = cv.take<T>(2 * PS);
     const size_t oFlags = cv.take<unsigned>(G);
-    const size_t oRed = cv.take<unsigned long long>(4 * (size_t)maxit);
+    const int redsw = std::max(maxit, amax);
+    const size_t oRed = cv.take<unsigned long long>(4 * (size_t)redsw);
     const size_t oOut = cv.take<int>(kOutWords);
     const size_t oAcc = cv.take<double>(4);
+    const size_t oEdges = cv.take<int>(active ? 2 * (size_t)std::max(ecap, 1ll) : 1);
+    const size_t oEcount = cv.take<int>(1);
+    const size_t oPart = cv.take<int>(active ? (size_t)Mmax * p : 1);
     Workspace ws;
     ws.stream = stream;
     ws.bytes = cv.off;
@@ -266,7 +320,86 @@ int fit_impl(concord_input kind, const void *X, int64_t n64, int64_t p64, double
     P.tstamp = opts ? reinterpret_cast<unsigned long long *>(opts->device_timestamps) : nullptr;
     P.tstamp_steps = (opts && opts->device_timestamps) ? opts->timestamp_steps : 0;
     CK_HIP(hipEventRecord(ev[4], stream));
-    CK_HIP(launch_sweep<T>(P, sh.threads, stream));
+    // active-set bookkeeping (host): reductions of the full sweeps, moves of
+    // all launches, active sweeps
+    std::vector<unsigned long long> full_red;
+    int64_t a_moved = 0, a_moved_d = 0;
+    int a_sweeps = 0;
+    if (!active) {
+        CK_HIP(launch_sweep<T>(P, sh.threads, stream));
+    } else {
+        int *edges = (int *)(B + oEdges), *ecount = (int *)(B + oEcount), *dpart = (int *)(B + oPart);
+        std::vector<unsigned long long> lred(4 * (size_t)redsw);
+        std::vector<int> hpart;  // partner table of the current colouring (host copy)
+        int lout[kOutWords];
+        // one launch of the sweep kernel from a clean barrier and reduction state
+        auto run = [&](int mx) -> int {
+            CK_HIP(launch_clear(flags, G, red, 4 * mx, out, 4, acc, 0, stream));
+            P.maxit = mx;
+            CK_HIP(launch_sweep<T>(P, sh.threads, stream));
+            CK_HIP(hipMemcpyAsync(lout, out, sizeof(lout), hipMemcpyDeviceToHost, stream));
+            CK_HIP(hipMemcpyAsync(lred.data(), red, sizeof(unsigned long long) * 4 * mx,
+                                  hipMemcpyDeviceToHost, stream));
+            CK_HIP(hipStreamSynchronize(stream));
+            for (int t = 0; t < lout[0] && t < mx; ++t) {
+                a_moved += (int64_t)lred[4 * (size_t)t + 2];
+                a_moved_d += (int64_t)lred[4 * (size_t)t + 3];
+            }
+            return CONCORD_OK;
+        };
+        for (;;) {
+            // a full sweep of Algorithm 1 decides convergence
+            P.part = nullptr;
+            P.m_tab = 0;
+            int rc = run(1);
+            if (rc)
+                return rc;
+            if (lout[0] >= 1)
+                for (int w = 0; w < 4; ++w)
+                    full_red.push_back(lred[w]);
+            if (lout[4] || lout[2] || lout[3] || lout[1] || (int)(full_red.size() / 4) >= maxit)
+                break;
+            // colour the support of the current Omega
+            CK_HIP(launch_finalize<T>(omp, omdp, sh.Gr, sh.Gc, sh.nr_max, W, p, (T)lambda,
+                                      (T *)omega, acc, nnz, out + 4, stream));
+            CK_HIP(launch_clear(nullptr, 0, nullptr, 0, ecount, 1, nullptr, 0, stream));
+            CK_HIP(launch_support_edges<T>((const T *)omega, p, ecount, edges, ecap, stream));
+            int ne = 0;
+            CK_HIP(hipMemcpyAsync(&ne, ecount, sizeof(int), hipMemcpyDeviceToHost, stream));
+            CK_HIP(hipStreamSynchronize(stream));
+            std::vector<int> he(2 * (size_t)std::max(ne, 1));
+            if (ne > 0) {
+                CK_HIP(hipMemcpyAsync(he.data(), edges, sizeof(int) * 2 * (size_t)ne,
+                                      hipMemcpyDeviceToHost, stream));
+                CK_HIP(hipStreamSynchronize(stream));
+            }
+            const int mt = greedy_colouring(he.data(), ne, p, &hpart);
+            CK_HIP(hipMemcpyAsync(dpart, hpart.data(), sizeof(int) * hpart.size(),
+                                  hipMemcpyHostToDevice, stream));
+            CK_HIP(hipStreamSynchronize(stream));
+            // the sweep layout of that colouring, from the dense Omega
+            CK_HIP(launch_init_omega<T>((const T *)omega, p, sh.Gr, sh.Gc, sh.nr_max, omp, omdp,
+                                        out + 4, stream, dpart, mt));
+            CK_HIP(launch_init_publish<T>(W, p, sh.Gr, sh.nr_max, pc, pd, stream, dpart, mt));
+            P.part = dpart;
+            P.m_tab = mt;
+            rc = run(amax);
+            if (rc)
+                return rc;
+            a_sweeps += lout[0];
+            if (lout[4] || lout[2] || lout[3])
+                break;
+            // back to Algorithm 1's layout
+            CK_HIP(launch_fill<T>((T *)omega, (long long)pp, T(0), stream));
+            CK_HIP(launch_scatter_omega<T>(omp, omdp, dpart, mt, sh.Gr, sh.Gc, sh.nr_max, p,
+                                           (T *)omega, stream));
+            CK_HIP(launch_init_omega<T>((const T *)omega, p, sh.Gr, sh.Gc, sh.nr_max, omp, omdp,
+                                        out + 4, stream));
+            CK_HIP(launch_init_publish<T>(W, p, sh.Gr, sh.nr_max, pc, pd, stream));
+        }
+        P.part = nullptr;
+        CK_HIP(launch_clear(nullptr, 0, nullptr, 0, nullptr, 0, acc, 4, stream));
+    }
     CK_HIP(hipEventRecord(ev[5], stream));
     CK_HIP(launch_finalize<T>(omp, omdp, sh.Gr, sh.Gc, sh.nr_max, W, p, (T)lambda, (T *)omega, acc,
                               nnz, out + 4, stream));
@@ -279,7 +412,7 @@ int fit_impl(concord_input kind, const void *X, int64_t n64, int64_t p64, double
     int hout[kOutWords];
     double hacc[2];
     unsigned long long hnnz = 0;
-    std::vector<unsigned long long> hred(4 * (size_t)maxit);
+    std::vector<unsigned long long> hred(4 * (size_t)redsw);
     CK_HIP(hipMemcpyAsync(hout, out, sizeof(hout), hipMemcpyDeviceToHost, stream));
     CK_HIP(hipMemcpyAsync(hacc, acc, sizeof(hacc), hipMemcpyDeviceToHost, stream));
     CK_HIP(hipMemcpyAsync(&hnnz, nnz, sizeof(hnnz), hipMemcpyDeviceToHost, stream));
@@ -291,7 +424,6 @@ int fit_impl(concord_input kind, const void *X, int64_t n64, int64_t p64, double
     if (kind == CONCORD_INPUT_Y)
         (void)hipEventElapsedTime(&ms_gram, ev[2], ev[3]);
     (void)hipEventElapsedTime(&ms_sweep, ev[4], ev[5]);
-    const int sweeps = hout[0];
 
     auto bits_to = [](unsigned long long u) -> double {
         if (sizeof(T) == 8) {
@@ -305,18 +437,34 @@ int fit_impl(concord_input kind, const void *X, int64_t n64, int64_t p64, double
         return (double)f;
     };
     double *trace = opts ? opts->delta_trace : nullptr;
-    if (trace)
-        for (int t = 0; t < sweeps && t < maxit; ++t)
-            trace[t] = bits_to(hred[4 * (size_t)t]);
     unsigned long long last[2] = {0, 0};
     int64_t moved = 0, moved_d = 0;
-    for (int t = 0; t < sweeps && t < maxit; ++t) {
-        moved += (int64_t)hred[4 * (size_t)t + 2];
-        moved_d += (int64_t)hred[4 * (size_t)t + 3];
-    }
-    if (sweeps > 0) {
-        last[0] = hred[4 * (size_t)(sweeps - 1)];
-        last[1] = hred[4 * (size_t)(sweeps - 1) + 1];
+    int sweeps = hout[0];
+    if (!active) {
+        if (trace)
+            for (int t = 0; t < sweeps && t < maxit; ++t)
+                trace[t] = bits_to(hred[4 * (size_t)t]);
+        for (int t = 0; t < sweeps && t < maxit; ++t) {
+            moved += (int64_t)hred[4 * (size_t)t + 2];
+            moved_d += (int64_t)hred[4 * (size_t)t + 3];
+        }
+        if (sweeps > 0) {
+            last[0] = hred[4 * (size_t)(sweeps - 1)];
+            last[1] = hred[4 * (size_t)(sweeps - 1) + 1];
+        }
+    } else {
+        // sweeps counts the full sweeps of Algorithm 1 (the ones that decide
+        // convergence); moves are those of every sweep
+        sweeps = (int)(full_red.size() / 4);
+        if (trace)
+            for (int t = 0; t < sweeps && t < maxit; ++t)
+                trace[t] = bits_to(full_red[4 * (size_t)t]);
+        moved = a_moved;
+        moved_d = a_moved_d;
+        if (sweeps > 0) {
+            last[0] = full_red[4 * (size_t)(sweeps - 1)];
+            last[1] = full_red[4 * (size_t)(sweeps - 1) + 1];
+        }
     }
     const double delta = bits_to(last[0]);
     const double gmax = bits_to(last[1]);
@@ -348,6 +496,7 @@ int fit_impl(concord_input kind, const void *X, int64_t n64, int64_t p64, double
         info->w_in_lds = sh.w_lds;
         info->block_threads = sh.threads;
         info->pending_depth = sh.depth;
+        info->active_sweeps = a_sweeps;
     }
     return status;
 }

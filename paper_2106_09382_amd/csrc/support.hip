@@ -57,27 +57,30 @@ __global__ void check_copy_kernel(const T *__restrict__ S, int p, T *__restrict_
 
 // Starting Omega in the sweep's layout: every workgroup's own copy of
 // omega_{i, partner_r(i)} for its rows and all colours, and of omega_ii.
-// omega0 == nullptr means the identity.
+// omega0 == nullptr means the identity.  part == nullptr: Algorithm 1's
+// schedule; else the mt-colour table part[r * p + i].
 template <typename T>
 __global__ void init_omega_kernel(const T *__restrict__ omega0, int p, int Gr, int Gc, int NR,
-                                  T *__restrict__ omp, T *__restrict__ omdp, int *__restrict__ err)
+                                  const int *__restrict__ part, int mt, T *__restrict__ omp,
+                                  T *__restrict__ omdp, int *__restrict__ err)
 {
     const Circle C = Circle::make(p);
     const int G = Gr * Gc;
-    const long long offd = (long long)G * C.m * NR;
+    const int M = part ? mt : C.m;
+    const long long offd = (long long)G * M * NR;
     const long long total = offd + (long long)G * NR;
     int bad = 0;
     for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
          e += (long long)gridDim.x * blockDim.x) {
         if (e < offd) {
-            const long long per = (long long)C.m * NR;
+            const long long per = (long long)M * NR;
             const int g = (int)(e / per);
             const long long rem = e - (long long)g * per;
             const int r = (int)(rem / NR), k = (int)(rem - (long long)r * NR);
             const int i = g / Gc + k * Gr;
             T w = T(0);
             if (omega0 && i < p) {
-                const int j = C.partner(r, i);
+                const int j = part ? part[(size_t)r * p + i] : C.partner(r, i);
                 if (j >= 0) {
                     w = omega0[(size_t)i * p + j];
                     if (!finite_v(w))
@@ -129,26 +132,28 @@ __global__ void clear_kernel(unsigned *__restrict__ flags, int nflags,
 // are group-major: row i at (i mod Gr) * NR + i / Gr, PS = Gr * NR per colour.
 template <typename T>
 __global__ void init_publish_kernel(const T *__restrict__ W, int p, int Gr, int NR,
-                                    T *__restrict__ pc, T *__restrict__ pd)
+                                    const int *__restrict__ part, int mt, T *__restrict__ pc,
+                                    T *__restrict__ pd)
 {
     using U = typename Sentinel<T>::U;
     const Circle C = Circle::make(p);
+    const int M = part ? mt : C.m;
     const long long PS = (long long)Gr * NR;
-    const long long npc = 2ll * C.m * PS;
+    const long long npc = 2ll * M * PS;
     U *pcu = reinterpret_cast<U *>(pc);
     U *pdu = reinterpret_cast<U *>(pd);
     for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < npc + 2 * PS;
          e += (long long)gridDim.x * blockDim.x) {
         if (e < PS) {
             const int i = (int)(e % NR) * Gr + (int)(e / NR);
-            const int j = (i < p) ? C.partner(0, i) : -1;
+            const int j = (i < p) ? (part ? part[i] : C.partner(0, i)) : -1;
             pc[e] = (j >= 0) ? W[(size_t)i * p + j] : T(0);
         } else if (e < npc) {
             pcu[e] = Sentinel<T>::bits;
         } else {
             const long long d = e - npc;
             const int i = (int)(d % NR) * Gr + (int)(d / NR);
-            if (d < PS && C.m == 1 && i < p)
+            if (d < PS && M == 1 && i < p)
                 pd[d] = W[(size_t)i * p + i];
             else
                 pdu[d] = Sentinel<T>::bits;
@@ -230,12 +235,12 @@ hipError_t launch_check_copy(const T *S, int p, T *W, bool copy_w, T *sd, int *e
 
 template <typename T>
 hipError_t launch_init_omega(const T *omega0, int p, int Gr, int Gc, int NR, T *omp, T *omdp,
-                             int *err, hipStream_t st)
+                             int *err, hipStream_t st, const int *part, int mt)
 {
     const Circle C = Circle::make(p);
-    const long long total = (long long)Gr * Gc * NR * (C.m + 1);
+    const long long total = (long long)Gr * Gc * NR * ((part ? mt : C.m) + 1);
     hipLaunchKernelGGL(init_omega_kernel<T>, dim3(grid_for(total, 8192)), dim3(kThreads), 0, st,
-                       omega0, p, Gr, Gc, NR, omp, omdp, err);
+                       omega0, p, Gr, Gc, NR, part, mt, omp, omdp, err);
     return hipGetLastError();
 }
 
@@ -251,12 +256,14 @@ hipError_t launch_clear(unsigned *flags, int nflags, unsigned long long *red, in
 }
 
 template <typename T>
-hipError_t launch_init_publish(const T *W, int p, int Gr, int NR, T *pc, T *pd, hipStream_t st)
+hipError_t launch_init_publish(const T *W, int p, int Gr, int NR, T *pc, T *pd, hipStream_t st,
+                               const int *part, int mt)
 {
     const Circle C = Circle::make(p);
     const long long PS = (long long)Gr * NR;
-    hipLaunchKernelGGL(init_publish_kernel<T>, dim3(grid_for(2ll * C.m * PS + 2 * PS, 8192)),
-                       dim3(kThreads), 0, st, W, p, Gr, NR, pc, pd);
+    const int M = part ? mt : C.m;
+    hipLaunchKernelGGL(init_publish_kernel<T>, dim3(grid_for(2ll * M * PS + 2 * PS, 8192)),
+                       dim3(kThreads), 0, st, W, p, Gr, NR, part, mt, pc, pd);
     return hipGetLastError();
 }
 
@@ -273,8 +280,9 @@ hipError_t launch_finalize(const T *omp, const T *omdp, int Gr, int Gc, int NR, 
 #define CONCORD_SUPPORT_INST(T)                                                                  \
     template hipError_t launch_check_copy<T>(const T *, int, T *, bool, T *, int *, hipStream_t); \
     template hipError_t launch_init_omega<T>(const T *, int, int, int, int, T *, T *, int *,     \
-                                             hipStream_t);                                       \
-    template hipError_t launch_init_publish<T>(const T *, int, int, int, T *, T *, hipStream_t); \
+                                             hipStream_t, const int *, int);                     \
+    template hipError_t launch_init_publish<T>(const T *, int, int, int, T *, T *, hipStream_t,  \
+                                               const int *, int);                                \
     template hipError_t launch_finalize<T>(const T *, const T *, int, int, int, const T *, int, T, \
                                            T *, double *, unsigned long long *, int *, hipStream_t);
 

@@ -12,17 +12,29 @@ constexpr int kErrNotPD = 2;      // some S_ii <= 0
 template <typename T>
 hipError_t launch_check_copy(const T *S, int p, T *W, bool copy_w, T *sd, int *err,
                              hipStream_t st);
+// part == nullptr: Algorithm 1's schedule; else the mt-colour partner table.
 template <typename T>
 hipError_t launch_init_omega(const T *omega0, int p, int Gr, int Gc, int NR, T *omp, T *omdp,
-                             int *err, hipStream_t st);
+                             int *err, hipStream_t st, const int *part = nullptr, int mt = 0);
 hipError_t launch_clear(unsigned *flags, int nflags, unsigned long long *red, int nred, int *out,
                         int nout, double *acc, int nacc, hipStream_t st);
 template <typename T>
-hipError_t launch_init_publish(const T *W, int p, int Gr, int NR, T *pc, T *pd, hipStream_t st);
+hipError_t launch_init_publish(const T *W, int p, int Gr, int NR, T *pc, T *pd, hipStream_t st,
+                               const int *part = nullptr, int mt = 0);
 template <typename T>
 hipError_t launch_finalize(const T *omp, const T *omdp, int Gr, int Gc, int NR, const T *W, int p,
                            T lam, T *omega, double *acc, unsigned long long *nnz, int *err,
                            hipStream_t st);
+
+// Active-set sweeps (active.hip): the support of a dense Omega as an edge
+// list (i < j, appended through an atomic counter, at most cap), and the
+// dense Omega from the sweep layout of a colour table (omega zero-filled first).
+template <typename T>
+hipError_t launch_support_edges(const T *omega, int p, int *count, int *edges, long long cap,
+                                hipStream_t st);
+template <typename T>
+hipError_t launch_scatter_omega(const T *omp, const T *omdp, const int *part, int mt, int Gr,
+                                int Gc, int NR, int p, T *omega, hipStream_t st);
 
 // Adjoint system of the implicit gradient (adjoint.hip).
 template <typename T>

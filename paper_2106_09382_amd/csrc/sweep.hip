@@ -189,17 +189,18 @@ struct RowNext {
 };
 
 template <typename T, bool WLDS>
-__device__ __forceinline__ void load_next(RowNext<T> &x, const Circle &C, int r1, int i, int k,
+__device__ __forceinline__ void load_next(RowNext<T> &x, const Circle &C, const int *part, int m,
+                                          int r1, int i, int k,
                                           int n, const int *pj, int D, int NR, int p, int c0,
                                           int c1, int nc, const T *__restrict__ S,
                                           const T *__restrict__ Wg, const T *wblk,
                                           const T *__restrict__ omp, const T *__restrict__ omdp,
                                           const T *__restrict__ adjg)
 {
-    const int m = C.m;
     const int rn1 = (r1 + 1 == m) ? 0 : r1 + 1;
-    x.j = C.partner(r1, i);
-    const int kn = C.partner(rn1, i);
+    // the schedule: Algorithm 1's round robin, or a given colouring's table
+    x.j = part ? part[(size_t)r1 * p + i] : C.partner(r1, i);
+    const int kn = part ? part[(size_t)rn1 * p + i] : C.partner(rn1, i);
     x.kn = (kn >= c0 && kn < c1) ? kn : -1;
     x.last = (r1 == m - 1);
     x.pubd = (rn1 == m - 1) && i >= c0 && i < c1;
@@ -327,7 +328,9 @@ __device__ void pcd_solve(const SweepParams<T> &P, int g, int G, unsigned char *
     using U = typename Sentinel<T>::U;
     constexpr U SENT = Sentinel<T>::bits;
     const Circle C = Circle::make(P.p);
-    const int p = P.p, m = C.m;
+    // colours per sweep: p_even - 1 for Algorithm 1's schedule, or those of
+    // the given colouring (P.part[r * p + i] = partner of i in colour r, -1 idle)
+    const int p = P.p, m = P.part ? P.m_tab : C.m;
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int a = g / P.Gc, b = g % P.Gc;
     const int Gr = P.Gr;
@@ -384,7 +387,7 @@ __device__ void pcd_solve(const SweepParams<T> &P, int g, int G, unsigned char *
         flushed[u] = false;
         const int k = tid + u * nthr;
         if (k < nr)
-            load_next<T, WLDS>(nx[u], C, 0, a + k * Gr, k, 0, pj, D, NR, p, c0, c1, nc, S, Wg,
+            load_next<T, WLDS>(nx[u], C, P.part, m, 0, a + k * Gr, k, 0, pj, D, NR, p, c0, c1, nc, S, Wg,
                                wblk, omp, omdp, adjg);
     }
     // adjoint mode: the diagonal right-hand side and denominator of each row
@@ -601,7 +604,7 @@ __device__ void pcd_solve(const SweepParams<T> &P, int g, int G, unsigned char *
                 // ---- operands of the row's next step.  The stored W entry is
                 // read before this step's rewrites (they start after the
                 // workgroup barrier below), so it is folded with all n entries.
-                load_next<T, WLDS>(nx[u], C, rn, i, k, n, pj, D, NR, p, c0, c1, nc, S, Wg, wblk,
+                load_next<T, WLDS>(nx[u], C, P.part, m, rn, i, k, n, pj, D, NR, p, c0, c1, nc, S, Wg, wblk,
                                    omp, omdp, adjg);
             }
 

@@ -75,6 +75,11 @@ struct SweepParams {
     T *const *omega_out;
     PathRec *rec;
     int g0;  // first workgroup of this problem in a batched launch
+    // Schedule: null for Algorithm 1's round robin (closed form); else an
+    // m_tab x p table, part[r * p + i] = partner of i in colour r (-1 idle),
+    // every colour a matching and m_tab >= 2 (single solves only).
+    const int *part;
+    int m_tab;
     // Adjoint system of the implicit gradient (null for a solve): adj_g in
     // omp's layout holds g_ij of the free pairs (NaN elsewhere); adj_gd and
     // adj_hd, one per row like omdp, hold g_ii and S_ii + 1 / omega_ii^2.
