@@ -35,6 +35,10 @@ and two side measurements on their own workloads:
 * `fp32`: the same solve in FP32 (S 100 MB + W 100 MB, the cache-resident
   regime), with a cache-resident copy bandwidth (a 64 MiB device copy,
   repeated) beside the HBM peak.
+* `active_set`: time to tolerance of the same workload at lambda 0.1 and 0.2,
+  plain Algorithm 1 against the active-set sweeps (full round-robin sweeps
+  decide convergence; between them, sweeps over a greedy colouring of the
+  support).
 * `backward`: the implicit gradient (concord_backward) at p = 2000, n = 1000,
   chain Omega_0, lambda = 0.15, L = |Omega-hat - Omega_0|_F^2, FP64, against the
   forward solve at the same tolerance.
@@ -219,6 +223,31 @@ def floor_measurement(Y, shape: dict, bytes_per_sweep: float, t_sweep_ms: float,
         "frac": t_floor / t_sweep_ms,
         "binds": "sync" if t_sync >= t_bw else "bandwidth",
     }
+
+
+def active_measurement(Y, tol: float, shape: dict) -> dict:
+    """Plain Algorithm 1 against the active-set sweeps, time to tolerance."""
+    import torch
+
+    from paper_2106_09382_amd import _lib
+
+    out = {}
+    for lam in (0.1, 0.2):
+        row = {}
+        for mode in ("plain", "active"):
+            best = None
+            for _ in range(2):
+                _, info = _lib.fit(Y, lam, tol, 500, kind="Y", check=False,
+                                   active_set=(mode == "active"), **shape)
+                torch.cuda.synchronize()
+                if best is None or info["elapsed_ms"] < best["elapsed_ms"]:
+                    best = info
+            row[mode] = {"ms": best["elapsed_ms"], "full_sweeps": best["sweeps"],
+                         "active_sweeps": best["active_sweeps"], "nnz_upper": best["nnz_upper"],
+                         "code": best["code"]}
+        row["speedup"] = row["plain"]["ms"] / row["active"]["ms"]
+        out[f"lambda_{lam}"] = row
+    return out
 
 
 def fp32_measurement(Y, lam: float, tol: float, shape: dict) -> dict:
@@ -446,6 +475,7 @@ def main() -> int:
         res["floor"] = floor_measurement(Y, shape, bytes_launch / max(sweeps, 1),
                                          float(np.mean(sweep_ms)) / max(sweeps, 1), m)
         res["fp32"] = fp32_measurement(Y, args.lam, args.tol, shape)
+        res["active_set"] = active_measurement(Y, args.tol, shape)
     if not args.no_batched:
         res["batched"] = batched_measurement(args.plain_all)
     if not args.no_backward:
