@@ -188,8 +188,8 @@ struct RowNext {
     T sv[kMaxDepth];
 };
 
-template <typename T, bool WLDS>
-__device__ __forceinline__ void load_next(RowNext<T> &x, const Circle &C, const int *part, int m,
+template <typename T, bool WLDS, bool TAB>
+__device__ __forceinline__ void load_next(RowNext<T> &x, const Circle &C, const int *part, int mt,
                                           int r1, int i, int k,
                                           int n, const int *pj, int D, int NR, int p, int c0,
                                           int c1, int nc, const T *__restrict__ S,
@@ -197,10 +197,17 @@ __device__ __forceinline__ void load_next(RowNext<T> &x, const Circle &C, const 
                                           const T *__restrict__ omp, const T *__restrict__ omdp,
                                           const T *__restrict__ adjg)
 {
-    const int rn1 = (r1 + 1 == m) ? 0 : r1 + 1;
     // the schedule: Algorithm 1's round robin, or a given colouring's table
-    x.j = part ? part[(size_t)r1 * p + i] : C.partner(r1, i);
-    const int kn = part ? part[(size_t)rn1 * p + i] : C.partner(rn1, i);
+    const int m = TAB ? mt : C.m;
+    const int rn1 = (r1 + 1 == m) ? 0 : r1 + 1;
+    int kn;
+    if constexpr (TAB) {
+        x.j = part[(size_t)r1 * p + i];
+        kn = part[(size_t)rn1 * p + i];
+    } else {
+        x.j = C.partner(r1, i);
+        kn = C.partner(rn1, i);
+    }
     x.kn = (kn >= c0 && kn < c1) ? kn : -1;
     x.last = (r1 == m - 1);
     x.pubd = (rn1 == m - 1) && i >= c0 && i < c1;
@@ -322,7 +329,7 @@ __device__ void end_of_lambda(const SweepParams<T> &P, int l, T lam, const Circl
 // omdp then hold U and v; P.adj_g holds g_ij per colour in omp's layout (NaN
 // for a pair that is not free) and P.adj_gd / P.adj_hd hold g_ii and
 // S_ii + 1/omega_ii^2 per row.
-template <typename T, bool WLDS, int RPT, int CPL, bool ADJ>
+template <typename T, bool WLDS, int RPT, int CPL, bool ADJ, bool TAB>
 __device__ void pcd_solve(const SweepParams<T> &P, int g, int G, unsigned char *smem_raw)
 {
     using U = typename Sentinel<T>::U;
@@ -330,7 +337,7 @@ __device__ void pcd_solve(const SweepParams<T> &P, int g, int G, unsigned char *
     const Circle C = Circle::make(P.p);
     // colours per sweep: p_even - 1 for Algorithm 1's schedule, or those of
     // the given colouring (P.part[r * p + i] = partner of i in colour r, -1 idle)
-    const int p = P.p, m = P.part ? P.m_tab : C.m;
+    const int p = P.p, m = TAB ? P.m_tab : C.m;
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int a = g / P.Gc, b = g % P.Gc;
     const int Gr = P.Gr;
@@ -387,8 +394,8 @@ __device__ void pcd_solve(const SweepParams<T> &P, int g, int G, unsigned char *
         flushed[u] = false;
         const int k = tid + u * nthr;
         if (k < nr)
-            load_next<T, WLDS>(nx[u], C, P.part, m, 0, a + k * Gr, k, 0, pj, D, NR, p, c0, c1, nc, S, Wg,
-                               wblk, omp, omdp, adjg);
+            load_next<T, WLDS, TAB>(nx[u], C, P.part, m, 0, a + k * Gr, k, 0, pj, D, NR, p, c0,
+                                    c1, nc, S, Wg, wblk, omp, omdp, adjg);
     }
     // adjoint mode: the diagonal right-hand side and denominator of each row
     T adj_gd[RPT], adj_hd[RPT];
@@ -604,8 +611,8 @@ __device__ void pcd_solve(const SweepParams<T> &P, int g, int G, unsigned char *
                 // ---- operands of the row's next step.  The stored W entry is
                 // read before this step's rewrites (they start after the
                 // workgroup barrier below), so it is folded with all n entries.
-                load_next<T, WLDS>(nx[u], C, P.part, m, rn, i, k, n, pj, D, NR, p, c0, c1, nc, S, Wg, wblk,
-                                   omp, omdp, adjg);
+                load_next<T, WLDS, TAB>(nx[u], C, P.part, m, rn, i, k, n, pj, D, NR, p, c0, c1,
+                                        nc, S, Wg, wblk, omp, omdp, adjg);
             }
 
             // ---- every row of the step is done; rewrite the rows whose lists are full
@@ -727,11 +734,11 @@ size_t sweep_lds_bytes(const SweepParams<T> &P)
     return bytes;
 }
 
-template <typename T, bool WLDS, int RPT, bool ADJ>
+template <typename T, bool WLDS, int RPT, bool ADJ, bool TAB>
 __global__ void __launch_bounds__(512) pcd_sweep_kernel(SweepParams<T> P)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    pcd_solve<T, WLDS, RPT, 2, ADJ>(P, blockIdx.x, gridDim.x, smem_raw);
+    pcd_solve<T, WLDS, RPT, 2, ADJ, TAB>(P, blockIdx.x, gridDim.x, smem_raw);
 }
 
 // Many independent problems in one launch: workgroup blockIdx.x serves
@@ -748,17 +755,19 @@ __global__ void __launch_bounds__(512)
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const SweepParams<T> P = descs[wg_problem[blockIdx.x]];
     const int g = (int)blockIdx.x - P.g0, G = P.Gr * P.Gc;
-    pcd_solve<T, false, 2, 4, false>(P, g, G, smem_raw);
+    pcd_solve<T, false, 2, 4, false, false>(P, g, G, smem_raw);
 }
 
 namespace {
 
-template <typename T, bool WLDS, bool ADJ>
+// The schedule is a template argument: Algorithm 1's round robin computes
+// partners in registers, a colouring table (forward solves only) loads them.
+template <typename T, bool WLDS, bool ADJ, bool TAB>
 const void *pick_kernel(int rpt)
 {
     if (rpt <= 1)
-        return (const void *)pcd_sweep_kernel<T, WLDS, 1, ADJ>;
-    return (const void *)pcd_sweep_kernel<T, WLDS, 2, ADJ>;
+        return (const void *)pcd_sweep_kernel<T, WLDS, 1, ADJ, TAB>;
+    return (const void *)pcd_sweep_kernel<T, WLDS, 2, ADJ, TAB>;
 }
 
 }  // namespace
@@ -771,10 +780,17 @@ hipError_t launch_sweep(const SweepParams<T> &P, int threads, hipStream_t stream
     SweepParams<T> arg = P;
     void *args[] = {&arg};
     const void *fn;
+    if (P.adj_g && P.part)
+        return hipErrorInvalidValue;
     if (P.adj_g)
-        fn = P.w_lds ? pick_kernel<T, true, true>(P.rpt) : pick_kernel<T, false, true>(P.rpt);
+        fn = P.w_lds ? pick_kernel<T, true, true, false>(P.rpt)
+                     : pick_kernel<T, false, true, false>(P.rpt);
+    else if (P.part)
+        fn = P.w_lds ? pick_kernel<T, true, false, true>(P.rpt)
+                     : pick_kernel<T, false, false, true>(P.rpt);
     else
-        fn = P.w_lds ? pick_kernel<T, true, false>(P.rpt) : pick_kernel<T, false, false>(P.rpt);
+        fn = P.w_lds ? pick_kernel<T, true, false, false>(P.rpt)
+                     : pick_kernel<T, false, false, false>(P.rpt);
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess)
         return e;
