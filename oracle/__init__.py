@@ -20,6 +20,9 @@ write them).  The helpers here are plain NumPy definitions:
 support, sweeps over it, full sweeps to decide convergence).
 ``oracle.backward`` holds the implicit gradient of the estimate (dL/dS and
 dL/dlam from the stationarity system on the active set, by a dense solve).
+``oracle.joint`` holds the joint estimation of two precision matrices with a
+fused penalty (Section 6): block coordinate descent on Algorithm 1's schedule,
+its objective and its optimality conditions.
 """
 from __future__ import annotations
 
@@ -69,6 +72,14 @@ def _load():
     lib.oracle_offdiag_update.restype = ctypes.c_double
     lib.oracle_diag_update.argtypes = [dp, dp, ctypes.c_int, ctypes.c_int]
     lib.oracle_diag_update.restype = ctypes.c_double
+    cd_ = ctypes.c_double
+    lib.oracle_joint_pair.argtypes = [cd_, cd_, cd_, cd_, cd_, cd_, dp]
+    lib.oracle_joint_pair.restype = None
+    lib.oracle_joint_diag.argtypes = [cd_, cd_, cd_, cd_, cd_, dp]
+    lib.oracle_joint_diag.restype = None
+    lib.oracle_joint_pcd.argtypes = [dp, dp, ctypes.c_int, cd_, cd_, cd_, ctypes.c_int, dp, dp,
+                                     dp, dp, dp, dp]
+    lib.oracle_joint_pcd.restype = ctypes.c_int
     _lib = lib
     return lib
 

@@ -30,6 +30,7 @@ __all__ = [
     "standardise_columns",
     "problem",
     "batched_problems",
+    "joint_problem",
     "lambda_path",
     "CONFIGS",
 ]
@@ -55,6 +56,10 @@ def er_precision(p: int, rng: np.random.Generator, edge_prob: float | None = Non
     The diagonal shift puts lambda_min at ``lam_min`` before the rescale to
     unit diagonal; afterwards lambda_min is lam_min / d with d the shift.
     """
+    return _unit_diagonal(_er_adjacency(p, rng, edge_prob, wlo, whi), lam_min)
+
+
+def _er_adjacency(p, rng, edge_prob, wlo, whi):
     if edge_prob is None:
         edge_prob = 3.0 / p
     iu, ju = np.triu_indices(p, 1)
@@ -65,6 +70,11 @@ def er_precision(p: int, rng: np.random.Generator, edge_prob: float | None = Non
     a = np.zeros((p, p))
     a[iu, ju] = mag * sgn
     a[ju, iu] = mag * sgn
+    return a
+
+
+def _unit_diagonal(a, lam_min):
+    p = a.shape[0]
     if p == 1:
         lmin = 0.0
     else:
@@ -156,3 +166,39 @@ def batched_problems(replicate: int = 0, count: int = 64, p_lo: int = 200,
         y = sample_y(om0, nb, rng)
         out.append(dict(p=pb, n=nb, graph="er", omega0=om0, y=y))
     return out
+
+
+def joint_problem(replicate: int = 0, p: int = 5000, n: int = 2000, changed: float = 0.1,
+                  wlo: float = 0.3, whi: float = 0.5) -> dict:
+    """Two populations whose graphs differ in a few edges (a differential network).
+
+    Population 1 is an Erdos-Renyi precision matrix as in ``er_precision``.
+    Population 2 keeps its edges and weights except round(changed * |E|)
+    edges, chosen uniformly, which are deleted, and as many new edges between
+    unconnected pairs, with weights U[wlo, whi] and random signs.  Each
+    adjacency matrix is shifted and rescaled to unit diagonal separately, and
+    each population draws its own n rows.  Seed 6000 + replicate; draw order:
+    population 1's graph, the deleted edges, the new pairs, their magnitudes
+    and signs, then Y_1, then Y_2.
+    """
+    rng = np.random.default_rng(6000 + replicate)
+    a1 = _er_adjacency(p, rng, None, wlo, whi)
+    iu, ju = np.triu_indices(p, 1)
+    edge = a1[iu, ju] != 0
+    eidx = np.flatnonzero(edge)
+    k = int(round(changed * eidx.size))
+    gone = rng.choice(eidx, size=k, replace=False) if k else np.zeros(0, dtype=np.int64)
+    free = np.flatnonzero(~edge)
+    new = rng.choice(free, size=k, replace=False) if k else np.zeros(0, dtype=np.int64)
+    mag = rng.uniform(wlo, whi, size=k)
+    sgn = np.where(rng.random(k) < 0.5, -1.0, 1.0)
+    a2 = a1.copy()
+    a2[iu[gone], ju[gone]] = 0.0
+    a2[ju[gone], iu[gone]] = 0.0
+    a2[iu[new], ju[new]] = mag * sgn
+    a2[ju[new], iu[new]] = mag * sgn
+    om1, om2 = _unit_diagonal(a1, 0.1), _unit_diagonal(a2, 0.1)
+    y1 = sample_y(om1, n, rng)
+    y2 = sample_y(om2, n, rng)
+    return dict(p=p, n=n, changed=changed, omega0=(om1, om2), y=(y1, y2),
+                seed=6000 + replicate)
