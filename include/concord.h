@@ -182,6 +182,71 @@ int concord_fit_batched_ex(int32_t B, concord_input kind, const void *const *X, 
                            int32_t maxit, concord_dtype dt, void *const *omega,
                            concord_info *info, void *stream, const concord_batch_options *opts);
 
+/* Result of one joint solve (concord_fit_joint). */
+typedef struct {
+    int32_t sweeps;         /* sweeps performed (the sweep that met the test counts) */
+    int32_t status;         /* CONCORD_OK, CONCORD_NOT_CONVERGED or a negative code */
+    double delta;           /* max |change| over both matrices in the last sweep */
+    double tol_eff;         /* tolerance applied (as in concord_info) */
+    int64_t nnz_upper[2];   /* #{i < j : omega^m_ij != 0} for m = 1, 2 */
+    int64_t differ_upper;   /* #{i < j : omega^1_ij != omega^2_ij} */
+    double objective;       /* the joint objective F(Omega_1, Omega_2) at the output */
+    double elapsed_ms;      /* device time of the call */
+    double gram_ms;         /* device time of the two Gram kernels (CONCORD_INPUT_Y), else 0 */
+    double sweep_ms;        /* device time of the persistent sweep kernel */
+    int64_t moved_pairs;    /* over sweeps and both populations: pairs i<j whose entry changed */
+    int64_t moved_diag;     /* ... and diagonals */
+    int32_t row_groups;     /* launch shape of each population: workgroups over rows of W */
+    int32_t col_slices;     /*   ... and over columns (2 row_groups col_slices in all) */
+    int32_t w_in_lds;
+    int32_t block_threads;
+    int32_t pending_depth;
+    int32_t reserved;
+} concord_joint_info;
+
+/*
+ * concord_fit_joint -- joint estimation of two sparse precision matrices
+ * that differ little (Section 6 of arXiv 2106.09382), on the S scale:
+ *   F(Omega_1, Omega_2) = sum_m [ -sum_i log omega^m_ii + 1/2 tr(Omega_m S_m Omega_m) ]
+ *                         + lambda1 sum_m sum_{i<j} |omega^m_ij|
+ *                         + lambda2 sum_{i<=j} |omega^1_ij - omega^2_ij|.
+ * Block coordinate descent over (omega^1_ij, omega^2_ij) on Algorithm 1's
+ * schedule: the pairs of a colour share no vertex, so their blocks are
+ * updated at once, each by its exact block minimiser; then every diagonal
+ * block (omega^1_ii, omega^2_ii); stop when the largest change over both
+ * matrices in a sweep is below tol.  lambda2 = 0 gives two independent
+ * CONCORD-PCD solves; a large lambda2 fuses them (both equal the solve on
+ * (S_1 + S_2) / 2).
+ *   kind, dt   as for concord_fit, for both populations
+ *   X1, X2     S_m (p x p) or Y_m (n_m x p) in device memory (may be the same)
+ *   n1, n2     rows of Y_1, Y_2 (CONCORD_INPUT_Y)
+ *   p          variables, >= 1 (the same in both populations)
+ *   lambda1    sparsity threshold on the S scale, finite, >= 0
+ *   lambda2    fused threshold on the S scale, finite, >= 0
+ *   tol, maxit as for concord_fit
+ *   omega0_1, omega0_2  start points (p x p, symmetric, positive diagonal)
+ *              or NULL for the identity, each independently
+ *   omega1, omega2  out, p x p each, distinct buffers
+ *   info       out (host, may be NULL)
+ * The launch runs 2 row_groups x col_slices workgroups (by default each
+ * population gets half the compute units).  Options (opts may be NULL):
+ * row_groups, col_slices, block_threads, w_in_lds, pending_depth and
+ * delta_trace as for concord_fit_ex; active_set, w_out and
+ * device_timestamps must be zero (CONCORD_EINVAL otherwise).
+ * Returns CONCORD_OK, CONCORD_NOT_CONVERGED or a negative code.
+ */
+int concord_fit_joint(concord_input kind, const void *X1, const void *X2, int64_t n1, int64_t n2,
+                      int64_t p, double lambda1, double lambda2, double tol, int32_t maxit,
+                      concord_dtype dt, const void *omega0_1, const void *omega0_2, void *omega1,
+                      void *omega2, concord_joint_info *info, void *stream);
+
+/* concord_fit_joint with explicit launch options (opts may be NULL). */
+int concord_fit_joint_ex(concord_input kind, const void *X1, const void *X2, int64_t n1,
+                         int64_t n2, int64_t p, double lambda1, double lambda2, double tol,
+                         int32_t maxit, concord_dtype dt, const void *omega0_1,
+                         const void *omega0_2, void *omega1, void *omega2,
+                         concord_joint_info *info, void *stream, const concord_options *opts);
+
 /*
  * concord_backward -- implicit gradient of the estimate (for training losses
  * and lambda tuning through a fit).  Given Omega-hat = concord_fit(S, lam)

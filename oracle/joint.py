@@ -120,3 +120,25 @@ def kkt(S1, S2, O1, O2, lam1: float, lam2: float) -> dict:
         ivs = [sub(y1 - y2, lam2), (-g1, -g1), (g2, g2)]
         worst_diag = max(worst_diag, _gap(ivs))
     return dict(pairs=worst_pair, diag=worst_diag)
+
+
+def block_update_at(S1, S2, O1, O2, i: int, j: int, lam1: float, lam2: float):
+    """The new (omega^1_ij, omega^2_ij) (i != j) or (omega^1_ii, omega^2_ii)
+    (i == j) that one block update would give at (Omega_1, Omega_2): the eq.
+    (3) numerators (or eq. (2) sums) as direct sums over rows i and j, then
+    the block minimiser.  O(p) per call, for spot checks at any size."""
+    S1, S2, O1, O2 = _f64(S1), _f64(S2), _f64(O1), _f64(O2)
+    if i == j:
+        c = []
+        for S, O in ((S1, O1), (S2, O2)):
+            row = O[i] * S[i]
+            c.append(float(row.sum() - row[i]))
+        return diag(S1[i, i], c[0], S2[i, i], c[1], lam2)
+    ab = []
+    for S, O in ((S1, O1), (S2, O2)):
+        # sum_{u != j} omega_iu S_ju + sum_{u != i} omega_uj S_iu
+        t1 = O[i] * S[j]
+        t2 = O[j] * S[i]
+        b = float(t1.sum() - t1[j] + t2.sum() - t2[i])
+        ab += [S[i, i] + S[j, j], b]
+    return pair(ab[0], ab[1], ab[2], ab[3], lam1, lam2)

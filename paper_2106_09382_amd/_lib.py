@@ -47,6 +47,34 @@ class ConcordInfo(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class ConcordJointInfo(ctypes.Structure):
+    _fields_ = [
+        ("sweeps", ctypes.c_int32),
+        ("status", ctypes.c_int32),
+        ("delta", ctypes.c_double),
+        ("tol_eff", ctypes.c_double),
+        ("nnz_upper", ctypes.c_int64 * 2),
+        ("differ_upper", ctypes.c_int64),
+        ("objective", ctypes.c_double),
+        ("elapsed_ms", ctypes.c_double),
+        ("gram_ms", ctypes.c_double),
+        ("sweep_ms", ctypes.c_double),
+        ("moved_pairs", ctypes.c_int64),
+        ("moved_diag", ctypes.c_int64),
+        ("row_groups", ctypes.c_int32),
+        ("col_slices", ctypes.c_int32),
+        ("w_in_lds", ctypes.c_int32),
+        ("block_threads", ctypes.c_int32),
+        ("pending_depth", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+    def as_dict(self) -> dict:
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        d["nnz_upper"] = (int(self.nnz_upper[0]), int(self.nnz_upper[1]))
+        return d
+
+
 class ConcordOptions(ctypes.Structure):
     _fields_ = [
         ("row_groups", ctypes.c_int32),
@@ -116,6 +144,13 @@ def load(path: str = LIB_PATH):
     lib.concord_backward_ex.restype = ctypes.c_int
     lib.concord_backward.argtypes = lib.concord_backward_ex.argtypes[:-1]
     lib.concord_backward.restype = ctypes.c_int
+    lib.concord_fit_joint_ex.argtypes = [ctypes.c_int, vp, vp, i64, i64, i64, dbl, dbl, dbl, i32,
+                                         ctypes.c_int, vp, vp, vp, vp,
+                                         ctypes.POINTER(ConcordJointInfo), vp,
+                                         ctypes.POINTER(ConcordOptions)]
+    lib.concord_fit_joint_ex.restype = ctypes.c_int
+    lib.concord_fit_joint.argtypes = lib.concord_fit_joint_ex.argtypes[:-1]
+    lib.concord_fit_joint.restype = ctypes.c_int
     lib.concord_gram.argtypes = [vp, i64, i64, ctypes.c_int, vp, vp]
     lib.concord_gram.restype = ctypes.c_int
     lib.concord_schedule.argtypes = [i64, ctypes.POINTER(ctypes.c_int32)]
@@ -224,6 +259,70 @@ def fit(X: torch.Tensor, lam: float, tol: float = 1e-6, maxit: int = 500, *, kin
     if check:
         _raise(code, "concord_fit")
     return out, d
+
+
+def fit_joint(X1: torch.Tensor, X2: torch.Tensor, lam1: float, lam2: float, tol: float = 1e-6,
+              maxit: int = 500, *, kind: str = "S", omega0=(None, None), outs=None,
+              stream=None, row_groups: int = 0, col_slices: int = 0, block_threads: int = 0,
+              w_in_lds: int = 0, pending_depth: int = 0, trace: bool = False,
+              check: bool = True):
+    """Joint estimation of two precision matrices with a fused penalty
+    (Section 6).  X1, X2 are S_1, S_2 (p x p) or, with kind='Y', Y_1, Y_2
+    (n_m x p).  Returns (omega_1, omega_2, info dict)."""
+    lib = load()
+    for t, nm in ((X1, "X1"), (X2, "X2")):
+        _check_dev(t, nm)
+        if t.dim() != 2:
+            raise ValueError(f"{nm} must be a matrix")
+    if X1.dtype != X2.dtype or X1.device != X2.device:
+        raise ValueError("X1 and X2 must share dtype and device")
+    dt = _dtype_code(X1)
+    if kind == "S":
+        if X1.shape[0] != X1.shape[1] or tuple(X2.shape) != tuple(X1.shape):
+            raise ValueError("S_1 and S_2 must be square and of one size")
+        p, n1, n2, kc = X1.shape[0], 0, 0, INPUT_S
+    elif kind == "Y":
+        if X1.shape[1] != X2.shape[1]:
+            raise ValueError("Y_1 and Y_2 must have the same number of columns")
+        p, n1, n2, kc = X1.shape[1], X1.shape[0], X2.shape[0], INPUT_Y
+    else:
+        raise ValueError("kind must be 'S' or 'Y'")
+    if outs is None:
+        outs = (torch.empty((p, p), dtype=X1.dtype, device=X1.device),
+                torch.empty((p, p), dtype=X1.dtype, device=X1.device))
+    for o in outs:
+        _check_dev(o, "out")
+        if o.dtype != X1.dtype or tuple(o.shape) != (p, p):
+            raise ValueError("outputs must be p x p with the inputs' dtype")
+    o0 = []
+    for o in omega0:
+        if o is None:
+            o0.append(None)
+            continue
+        _check_dev(o, "omega0")
+        if o.dtype != X1.dtype or tuple(o.shape) != (p, p):
+            raise ValueError("omega0 must be p x p with the inputs' dtype")
+        o0.append(ctypes.c_void_p(o.data_ptr()))
+    info = ConcordJointInfo()
+    opts = ConcordOptions(row_groups, col_slices, block_threads, w_in_lds, pending_depth, None,
+                          None, 0, 0, None, 0, 0)
+    tr = None
+    if trace:
+        tr = (ctypes.c_double * int(maxit))()
+        opts.delta_trace = ctypes.cast(tr, ctypes.POINTER(ctypes.c_double))
+    with torch.cuda.device(X1.device):
+        code = lib.concord_fit_joint_ex(
+            kc, ctypes.c_void_p(X1.data_ptr()), ctypes.c_void_p(X2.data_ptr()), n1, n2, p,
+            float(lam1), float(lam2), float(tol), int(maxit), dt, o0[0], o0[1],
+            ctypes.c_void_p(outs[0].data_ptr()), ctypes.c_void_p(outs[1].data_ptr()),
+            ctypes.byref(info), _stream_handle(stream), ctypes.byref(opts))
+    d = info.as_dict()
+    d["code"] = code
+    if tr is not None:
+        d["delta_trace"] = [tr[k] for k in range(max(0, info.sweeps))]
+    if check:
+        _raise(code, "concord_fit_joint")
+    return outs[0], outs[1], d
 
 
 def fit_batched(Xs, lambdas, tol: float = 1e-6, maxit: int = 500, *, kind: str = "S",

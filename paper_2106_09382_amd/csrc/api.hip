@@ -75,13 +75,13 @@ int max_shared_per_block()
 }
 
 // Launch shape for one solve of size p.  Small problems run in one
-// workgroup; larger ones over a grid of Gr x Gc workgroups, one per CU, with
-// W blocks in LDS when they fit.  Rows of a workgroup are dealt to threads,
-// at most four per thread.
+// workgroup; larger ones over a grid of Gr x Gc workgroups, one per CU (of
+// the 1 / cu_share of the CUs the solve gets), with W blocks in LDS when they
+// fit.  Rows of a workgroup are dealt to threads, at most two per thread.
 template <typename T>
-int choose_shape(int p, const concord_options *o, Shape *sh)
+int choose_shape(int p, const concord_options *o, Shape *sh, int cu_share = 1)
 {
-    const int cus = std::max(1, cu_count());
+    const int cus = std::max(1, cu_count() / cu_share);
     int Gr = o ? o->row_groups : 0, Gc = o ? o->col_slices : 0;
     int threads = o ? o->block_threads : 0;
     int wl = o ? o->w_in_lds : 0;
@@ -1032,6 +1032,226 @@ int batched_impl(int B, concord_input kind, const void *const *X, const int64_t 
     return worst;
 }
 
+// ---------------------------------------------------------------- joint
+
+// Joint estimation of two precision matrices (Section 6): per population the
+// set-up of a single solve plus a copy of the other population's starting
+// omega in the layout of this population's workgroups, one persistent launch
+// of both, then each population's dense output and the fused term.
+template <typename T>
+int joint_impl(concord_input kind, const void *const X[2], const int64_t n[2], int64_t p64,
+               double lam1, double lam2, double tol, int32_t maxit, const void *const omega0[2],
+               void *const omega[2], concord_joint_info *info, hipStream_t stream,
+               const concord_options *opts)
+{
+    const int p = (int)p64;
+    if (opts && (opts->active_set || opts->w_out || opts->device_timestamps))
+        return CONCORD_EINVAL;
+    Shape sh;
+    int rc = choose_shape<T>(p, opts, &sh, 2);
+    if (rc)
+        return rc;
+    const Circle C = Circle::make(p);
+    const int G = sh.Gr * sh.Gc;
+
+    hipEvent_t ev[6] = {};
+    struct EvGuard {
+        hipEvent_t *e;
+        ~EvGuard()
+        {
+            for (int k = 0; k < 6; ++k)
+                if (e[k])
+                    (void)hipEventDestroy(e[k]);
+        }
+    } evg{ev};
+    for (int k = 0; k < 6; ++k)
+        CK_HIP(hipEventCreate(&ev[k]));
+    CK_HIP(hipEventRecord(ev[0], stream));
+
+    Carver cv;
+    const size_t pp = (size_t)p * p;
+    const size_t PS = (size_t)sh.Gr * sh.nr_max;
+    size_t oS[2], oW[2], oOmp[2], oOmdp[2], oSd[2], oPc[2], oPd[2], oOx[2], oOdx[2];
+    for (int m = 0; m < 2; ++m) {
+        oS[m] = (kind == CONCORD_INPUT_Y) ? cv.take<T>(pp) : 0;
+        oW[m] = cv.take<T>(pp);
+        oOmp[m] = cv.take<T>((size_t)G * C.m * sh.nr_max);
+        oOmdp[m] = cv.take<T>((size_t)G * sh.nr_max);
+        oOx[m] = cv.take<T>((size_t)G * C.m * sh.nr_max);
+        oOdx[m] = cv.take<T>((size_t)G * sh.nr_max);
+        oSd[m] = cv.take<T>(p);
+        oPc[m] = cv.take<T>(2 * (size_t)C.m * PS);
+        oPd[m] = cv.take<T>(2 * PS);
+    }
+    const size_t oFlags = cv.take<unsigned>(2 * (size_t)G);
+    const size_t oRed = cv.take<unsigned long long>(4 * (size_t)maxit);
+    const size_t oOut = cv.take<int>(kOutWords);
+    const size_t oAcc = cv.take<double>(8);  // [0..2] objectives and fused term, [4..6] counts
+    Workspace ws;
+    ws.stream = stream;
+    ws.bytes = cv.off;
+    {
+        hipError_t e = hipMallocAsync(&ws.base, ws.bytes, stream);
+        if (e != hipSuccess) {
+            ws.base = nullptr;
+            return map_hip(e);
+        }
+    }
+    char *B = (char *)ws.base;
+    T *S[2], *W[2], *omp[2], *omdp[2], *ox[2], *odx[2], *sd[2], *pc[2], *pd[2];
+    for (int m = 0; m < 2; ++m) {
+        S[m] = (kind == CONCORD_INPUT_Y) ? (T *)(B + oS[m]) : (T *)X[m];
+        W[m] = (T *)(B + oW[m]);
+        omp[m] = (T *)(B + oOmp[m]);
+        omdp[m] = (T *)(B + oOmdp[m]);
+        ox[m] = (T *)(B + oOx[m]);
+        odx[m] = (T *)(B + oOdx[m]);
+        sd[m] = (T *)(B + oSd[m]);
+        pc[m] = (T *)(B + oPc[m]);
+        pd[m] = (T *)(B + oPd[m]);
+    }
+    unsigned *flags = (unsigned *)(B + oFlags);
+    unsigned long long *red = (unsigned long long *)(B + oRed);
+    int *out = (int *)(B + oOut);
+    double *acc = (double *)(B + oAcc);
+    unsigned long long *cnt = (unsigned long long *)(acc + 4);
+
+    CK_HIP(launch_clear(flags, 2 * G, red, 4 * maxit, out, kOutWords, acc, 8, stream));
+    if (kind == CONCORD_INPUT_Y) {
+        CK_HIP(hipEventRecord(ev[2], stream));
+        for (int m = 0; m < 2; ++m)
+            CK_HIP(launch_gram<T>((const T *)X[m], (int)n[m], p, S[m], stream));
+        CK_HIP(hipEventRecord(ev[3], stream));
+    }
+    for (int m = 0; m < 2; ++m) {
+        CK_HIP(launch_check_copy<T>(S[m], p, W[m], omega0[m] == nullptr, sd[m], out + 4, stream));
+        if (omega0[m])
+            CK_HIP(launch_atb<T>((const T *)omega0[m], S[m], p, p, p, W[m], stream));
+        CK_HIP(launch_init_omega<T>((const T *)omega0[m], p, sh.Gr, sh.Gc, sh.nr_max, omp[m],
+                                    omdp[m], out + 4, stream));
+        CK_HIP(launch_init_omega<T>((const T *)omega0[1 - m], p, sh.Gr, sh.Gc, sh.nr_max, ox[m],
+                                    odx[m], out + 4, stream));
+        CK_HIP(launch_init_publish<T>(W[m], p, sh.Gr, sh.nr_max, pc[m], pd[m], stream));
+    }
+
+    SweepParams<T> P[2];
+    for (int m = 0; m < 2; ++m) {
+        SweepParams<T> &Q = P[m];
+        memset(&Q, 0, sizeof(Q));
+        Q.S = S[m];
+        Q.sd = sd[m];
+        Q.W = W[m];
+        Q.omp = omp[m];
+        Q.omdp = omdp[m];
+        Q.pc = pc[m];
+        Q.pd = pd[m];
+        Q.flags = flags;
+        Q.red = red;
+        Q.out = out;
+        Q.p = p;
+        Q.Gr = sh.Gr;
+        Q.Gc = sh.Gc;
+        Q.maxit = maxit;
+        Q.w_lds = sh.w_lds;
+        Q.nr_max = sh.nr_max;
+        Q.nc_max = sh.nc_max;
+        Q.depth = sh.depth;
+        Q.rpt = sh.rpt;
+        Q.lam = (T)lam1;
+        Q.tol = (T)tol;
+        Q.tol_coef = (sizeof(T) == 4) ? T(16.0 * 1.1920928955078125e-07) : T(0);
+        Q.spin_limit = kSpinLimit;
+        Q.jo_S = S[1 - m];
+        Q.jo_sd = sd[1 - m];
+        Q.jo_pc = pc[1 - m];
+        Q.jo_pd = pd[1 - m];
+        Q.jo_omp = ox[m];
+        Q.jo_omdp = odx[m];
+        Q.lam2 = (T)lam2;
+        Q.pop = m;
+    }
+    CK_HIP(hipEventRecord(ev[4], stream));
+    CK_HIP(launch_sweep_joint<T>(P[0], P[1], sh.threads, stream));
+    CK_HIP(hipEventRecord(ev[5], stream));
+    for (int m = 0; m < 2; ++m)
+        CK_HIP(launch_finalize<T>(omp[m], omdp[m], sh.Gr, sh.Gc, sh.nr_max, W[m], p, (T)lam1,
+                                  (T *)omega[m], acc + m, cnt + m, out + 4, stream));
+    CK_HIP(launch_joint_summary<T>((const T *)omega[0], (const T *)omega[1], p, (T)lam2, acc + 2,
+                                   cnt + 2, stream));
+    CK_HIP(hipEventRecord(ev[1], stream));
+
+    int hout[kOutWords];
+    double hacc[8];
+    std::vector<unsigned long long> hred(4 * (size_t)maxit);
+    CK_HIP(hipMemcpyAsync(hout, out, sizeof(hout), hipMemcpyDeviceToHost, stream));
+    CK_HIP(hipMemcpyAsync(hacc, acc, sizeof(hacc), hipMemcpyDeviceToHost, stream));
+    CK_HIP(hipMemcpyAsync(hred.data(), red, sizeof(unsigned long long) * hred.size(),
+                          hipMemcpyDeviceToHost, stream));
+    CK_HIP(hipStreamSynchronize(stream));
+    unsigned long long hcnt[4];
+    memcpy(hcnt, hacc + 4, sizeof(hcnt));
+    float ms = 0.f, ms_gram = 0.f, ms_sweep = 0.f;
+    (void)hipEventElapsedTime(&ms, ev[0], ev[1]);
+    if (kind == CONCORD_INPUT_Y)
+        (void)hipEventElapsedTime(&ms_gram, ev[2], ev[3]);
+    (void)hipEventElapsedTime(&ms_sweep, ev[4], ev[5]);
+
+    auto bits_to = [](unsigned long long u) -> double {
+        if (sizeof(T) == 8) {
+            double d;
+            memcpy(&d, &u, 8);
+            return d;
+        }
+        uint32_t w = (uint32_t)u;
+        float f;
+        memcpy(&f, &w, 4);
+        return (double)f;
+    };
+    const int sweeps = hout[0];
+    double *trace = opts ? opts->delta_trace : nullptr;
+    int64_t moved = 0, moved_d = 0;
+    for (int t = 0; t < sweeps && t < maxit; ++t) {
+        if (trace)
+            trace[t] = bits_to(hred[4 * (size_t)t]);
+        moved += (int64_t)hred[4 * (size_t)t + 2];
+        moved_d += (int64_t)hred[4 * (size_t)t + 3];
+    }
+    const double delta = sweeps > 0 ? bits_to(hred[4 * (size_t)(sweeps - 1)]) : 0.0;
+    const double gmax = sweeps > 0 ? bits_to(hred[4 * (size_t)(sweeps - 1) + 1]) : 0.0;
+    const double tol_eff = std::max(tol, (double)P[0].tol_coef * gmax);
+    int status;
+    if (hout[4] & kErrNotPD)
+        status = CONCORD_ENOTPD;
+    else if (hout[4] & kErrNonFinite)
+        status = CONCORD_ENONFINITE;
+    else if (hout[2] || hout[3])
+        status = CONCORD_EDEVICE;
+    else
+        status = hout[1] ? CONCORD_OK : CONCORD_NOT_CONVERGED;
+    if (info) {
+        memset(info, 0, sizeof(*info));
+        info->sweeps = sweeps;
+        info->status = status;
+        info->delta = delta;
+        info->tol_eff = tol_eff;
+        info->nnz_upper[0] = (int64_t)hcnt[0];
+        info->nnz_upper[1] = (int64_t)hcnt[1];
+        info->differ_upper = (int64_t)hcnt[2];
+        info->objective = hacc[0] + hacc[1] + hacc[2];
+        info->elapsed_ms = ms;
+        info->gram_ms = ms_gram;
+        info->sweep_ms = ms_sweep;
+        info->moved_pairs = moved;
+        info->moved_diag = moved_d;
+        info->row_groups = sh.Gr;
+        info->col_slices = sh.Gc;
+        info->w_in_lds = sh.w_lds;
+        info->block_threads = sh.threads;
+        info->pending_depth = sh.depth;
+    }
+    return status;
+}
+
 int validate(concord_input kind, const void *X, int64_t n, int64_t p, double lambda, double tol,
              int32_t maxit, concord_dtype dt, void *omega)
 {
@@ -1084,6 +1304,46 @@ extern "C" int concord_fit(concord_input kind, const void *X, int64_t n, int64_t
 {
     return concord_fit_ex(kind, X, n, p, lambda, tol, maxit, dt, omega0, omega, info, stream,
                           nullptr);
+}
+
+extern "C" int concord_fit_joint_ex(concord_input kind, const void *X1, const void *X2,
+                                    int64_t n1, int64_t n2, int64_t p, double lambda1,
+                                    double lambda2, double tol, int32_t maxit, concord_dtype dt,
+                                    const void *omega0_1, const void *omega0_2, void *omega1,
+                                    void *omega2, concord_joint_info *info, void *stream,
+                                    const concord_options *opts)
+{
+    int rc = validate(kind, X1, n1, p, lambda1, tol, maxit, dt, omega1);
+    if (!rc)
+        rc = validate(kind, X2, n2, p, lambda2, tol, maxit, dt, omega2);
+    if (!rc && omega1 == omega2)
+        rc = CONCORD_EINVAL;
+    if (rc) {
+        if (info) {
+            memset(info, 0, sizeof(*info));
+            info->status = rc;
+        }
+        return rc;
+    }
+    const void *const X[2] = {X1, X2};
+    const int64_t n[2] = {n1, n2};
+    const void *const o0[2] = {omega0_1, omega0_2};
+    void *const om[2] = {omega1, omega2};
+    hipStream_t st = (hipStream_t)stream;
+    if (dt == CONCORD_F64)
+        return joint_impl<double>(kind, X, n, p, lambda1, lambda2, tol, maxit, o0, om, info, st,
+                                  opts);
+    return joint_impl<float>(kind, X, n, p, lambda1, lambda2, tol, maxit, o0, om, info, st, opts);
+}
+
+extern "C" int concord_fit_joint(concord_input kind, const void *X1, const void *X2, int64_t n1,
+                                 int64_t n2, int64_t p, double lambda1, double lambda2,
+                                 double tol, int32_t maxit, concord_dtype dt,
+                                 const void *omega0_1, const void *omega0_2, void *omega1,
+                                 void *omega2, concord_joint_info *info, void *stream)
+{
+    return concord_fit_joint_ex(kind, X1, X2, n1, n2, p, lambda1, lambda2, tol, maxit, dt,
+                                omega0_1, omega0_2, omega1, omega2, info, stream, nullptr);
 }
 
 extern "C" int concord_fit_batched_ex(int32_t B, concord_input kind, const void *const *X,

@@ -50,4 +50,10 @@ template <typename T>
 hipError_t launch_adjoint_output(const T *M, const T *V, const T *om, int p, T *gS, double *acc,
                                  int *err, hipStream_t st);
 
+// Joint estimation (joint.hip): over i <= j, acc += lam2 |omega^1_ij -
+// omega^2_ij| and differ += [omega^1_ij != omega^2_ij] for i < j.
+template <typename T>
+hipError_t launch_joint_summary(const T *o1, const T *o2, int p, T lam2, double *acc,
+                                unsigned long long *differ, hipStream_t st);
+
 }  // namespace concord

@@ -1,726 +1,8 @@
-// Persistent CONCORD-PCD sweep kernel (Algorithm 1 of arXiv 2106.09382) for gfx950.
-//
-// Method.  For a pair (i, j) of colour r, eq. (3)'s numerator is
-//   b_ij = sum_{u != j} omega_iu S_ju + sum_{u != i} omega_uj S_iu
-//        = W_ij + W_ji - (S_ii + S_jj) omega_ij,           W = Omega S,
-// because Omega and S are symmetric ((S Omega)_ij = W_ji).  Changing
-// omega_ij = omega_ji by d changes only rows i and j of W: W_i. += d S_j. and
-// W_j. += d S_i..  For the diagonal step, eq. (2)'s sum is
-// c_i = W_ii - S_ii omega_ii, and changing omega_ii by d gives W_i. += d S_i..
-// So each pair costs O(1) to evaluate plus a row update when it moves,
-// instead of two length-p sums.
-//
-// Work split.  Workgroup g = a * Gc + b owns rows i = a (mod Gr) of W
-// restricted to column slice b (in LDS when the block fits, else in HBM where
-// only this workgroup touches it).  It keeps its own copy of omega for those
-// rows (every workgroup of a row group computes the same changes from the
-// same bits, so the copies stay identical).
-//
-// Synchronisation.  Colour r of a sweep needs, for pair (i, j), the entries
-// W_ij and W_ji as they stand after colour r - 1.  The workgroup owning
-// (row i, column j) publishes W_ij into a slot of `pc` as soon as its colour
-// r - 1 change is known; the readers poll that slot until the sentinel is
-// gone.  So colours are ordered by point-to-point waits, not by grid
-// barriers; one grid barrier per sweep carries the convergence test.  The
-// diagonal step is folded into the last colour: W_ii is published one colour
-// early (slot `pd`) and every workgroup of the row group finishes c_i itself.
-//
-// Deferred row updates.  A change of row i only has to reach W_ik by the time
-// W_ik is next published.  Each row keeps a list of pending (source row,
-// change) updates; a published entry is the stored W_ik with the pending
-// updates applied on the fly (same fused multiply-adds, same order), and the
-// whole row segment is rewritten only when the list fills.  The results are
-// bit-identical to applying every update at once; HBM traffic for W drops by
-// the list depth.
-//
-// Convergence.  Each entry of Omega changes exactly once per sweep, so
-// |Omega^(t) - Omega^(t-1)|_inf is the max |change| over the sweep; it is
-// reduced with one atomic max per workgroup, and read by every workgroup
-// after the sweep's grid barrier, so all agree on when to stop.
-#include "device_common.hpp"
-#include "schedule.hpp"
-#include "sweep.hpp"
+// Kernels and launchers of the persistent CONCORD-PCD sweep (the solve
+// itself, shared with the joint two-population kernel, is in sweep_solve.hpp).
+#include "sweep_solve.hpp"
 
 namespace concord {
-
-namespace {
-
-constexpr int kMaxDepth = 8;  // longest pending list (registers hold one S value per entry)
-
-// Sweep barrier: workgroup g stores the epoch into flags[g]; wave 0 of every
-// workgroup polls all flags.  Bounded: after spin_limit polls (or when any
-// workgroup has raised the abort word) it gives up and reports failure.
-template <typename T>
-__device__ bool sweep_barrier(const SweepParams<T> &P, unsigned epoch, int *s_fail, int g, int G)
-{
-    wait_stores();
-    __syncthreads();
-    if (G > 1) {
-        if (threadIdx.x == 0)
-            st_dev(&P.flags[g], epoch);
-        if (threadIdx.x < 64) {
-            long long spins = 0;
-            for (;;) {
-                int ok = 1;
-                for (int g = threadIdx.x; g < G; g += 64)
-                    ok &= (ld_dev(&P.flags[g]) >= epoch) ? 1 : 0;
-                if (__all(ok))
-                    break;
-                if (++spins > P.spin_limit || ld_dev(&P.out[3]) != 0) {
-                    if (threadIdx.x == 0) {
-                        st_dev(&P.out[3], 1);
-                        *s_fail = 1;
-                    }
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(1);
-            }
-        }
-        __syncthreads();
-    }
-    return *s_fail == 0;
-}
-
-template <typename T>
-__device__ __forceinline__ T block_max(T v, T *scratch)
-{
-    for (int off = 32; off > 0; off >>= 1) {
-        T o = __shfl_xor(v, off, 64);
-        v = (o > v || o != o) ? o : v;
-    }
-    const int wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    if ((threadIdx.x & 63) == 0)
-        scratch[wv] = v;
-    __syncthreads();
-    T r = scratch[0];
-    for (int w = 1; w < nw; ++w)
-        r = (scratch[w] > r || scratch[w] != scratch[w]) ? scratch[w] : r;
-    __syncthreads();
-    return r;
-}
-
-__device__ __forceinline__ unsigned block_sum(unsigned v, unsigned *scratch)
-{
-    for (int off = 32; off > 0; off >>= 1)
-        v += __shfl_xor(v, off, 64);
-    const int wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    if ((threadIdx.x & 63) == 0)
-        scratch[wv] = v;
-    __syncthreads();
-    unsigned r = 0;
-    for (int w = 0; w < nw; ++w)
-        r += scratch[w];
-    __syncthreads();
-    return r;
-}
-
-template <typename T>
-__device__ __forceinline__ T as_value(typename Sentinel<T>::U u)
-{
-    T v;
-    __builtin_memcpy(&v, &u, sizeof(T));
-    return v;
-}
-
-// Rewrites the segments of the listed rows with their pending updates:
-// W_ic <- fma(d_e, S_{src_e, c}, ...) in list order, for c in the slice.
-// Work is cut into (row, 64 * CPL column chunk) units dealt out to the waves;
-// each lane handles CPL columns 64 apart (every load is one coalesced row
-// segment), so CPL * (n + 1) loads are in flight per lane.
-template <typename T, bool WLDS, int CPL>
-__device__ void flush_rows(const int *rows, int nrows, const int *pj, const T *pdl,
-                           const int *np, int D, int a, int Gr, int p, int c0, int nc,
-                           const T *__restrict__ S, T *__restrict__ Wg, T *wblk)
-{
-    constexpr int CW = 64 * CPL;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    const int chunks = (nc + CW - 1) / CW;
-    const int units = nrows * chunks;
-    for (int u = wv; u < units; u += nw) {
-        const int fr = u / chunks, ch = u - fr * chunks;
-        const int k = rows[fr];
-        const int i = a + k * Gr;
-        const int n = np[k];
-        const int cl = ch * CW + lane;
-        T sv[kMaxDepth][CPL];
-#pragma unroll
-        for (int e = 0; e < kMaxDepth; ++e) {
-            if (e < n) {
-                const T *row = S + (size_t)pj[k * D + e] * p + c0;
-#pragma unroll
-                for (int q = 0; q < CPL; ++q)
-                    sv[e][q] = (cl + 64 * q < nc) ? row[cl + 64 * q] : T(0);
-            }
-        }
-        T *wr = WLDS ? &wblk[(size_t)k * nc] : &Wg[(size_t)i * p + c0];
-        T v[CPL];
-#pragma unroll
-        for (int q = 0; q < CPL; ++q)
-            v[q] = (cl + 64 * q < nc) ? wr[cl + 64 * q] : T(0);
-#pragma unroll
-        for (int e = 0; e < kMaxDepth; ++e) {
-            if (e < n) {
-                const T d = pdl[k * D + e];
-#pragma unroll
-                for (int q = 0; q < CPL; ++q)
-                    v[q] = fma(d, sv[e][q], v[q]);
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < CPL; ++q)
-            if (cl + 64 * q < nc)
-                wr[cl + 64 * q] = v[q];
-    }
-}
-
-// Operands of one row's next colour step that do not depend on that step's
-// change, loaded one step ahead so that their latency overlaps the previous
-// step's synchronisation and row rewrites.
-template <typename T>
-struct RowNext {
-    int j;        // partner in the step (-1: idle)
-    int kn;       // column published by the step (-1: none in this slice)
-    int n;        // pending entries the published value folds in
-    bool last;    // the step is the last colour (diagonal step follows)
-    bool pubd;    // the step publishes W_ii for the following last colour
-    T w, od, s_ji, wb, s_jn, s_in;
-    T g;          // adjoint mode: right-hand side of the pair (NaN: pair not free)
-    T sv[kMaxDepth];
-};
-
-template <typename T, bool WLDS, bool TAB>
-__device__ __forceinline__ void load_next(RowNext<T> &x, const Circle &C, const int *part, int mt,
-                                          int r1, int i, int k,
-                                          int n, const int *pj, int D, int NR, int p, int c0,
-                                          int c1, int nc, const T *__restrict__ S,
-                                          const T *__restrict__ Wg, const T *wblk,
-                                          const T *__restrict__ omp, const T *__restrict__ omdp,
-                                          const T *__restrict__ adjg)
-{
-    // the schedule: Algorithm 1's round robin, or a given colouring's table
-    const int m = TAB ? mt : C.m;
-    const int rn1 = (r1 + 1 == m) ? 0 : r1 + 1;
-    int kn;
-    if constexpr (TAB) {
-        x.j = part[(size_t)r1 * p + i];
-        kn = part[(size_t)rn1 * p + i];
-    } else {
-        x.j = C.partner(r1, i);
-        kn = C.partner(rn1, i);
-    }
-    x.kn = (kn >= c0 && kn < c1) ? kn : -1;
-    x.last = (r1 == m - 1);
-    x.pubd = (rn1 == m - 1) && i >= c0 && i < c1;
-    x.n = n;
-    x.w = (x.j >= 0) ? omp[(size_t)r1 * NR + k] : T(0);
-    x.g = (adjg && x.j >= 0) ? adjg[(size_t)r1 * NR + k] : T(0);
-    x.od = x.last ? omdp[k] : T(0);
-    x.s_ji = (x.j >= 0 && (x.last || x.pubd)) ? S[(size_t)x.j * p + i] : T(0);
-    if (x.kn >= 0) {
-        x.wb = WLDS ? wblk[(size_t)k * nc + (x.kn - c0)] : Wg[(size_t)i * p + x.kn];
-#pragma unroll
-        for (int e = 0; e < kMaxDepth; ++e)
-            if (e < n)
-                x.sv[e] = S[(size_t)pj[k * D + e] * p + x.kn];
-        x.s_jn = (x.j >= 0) ? S[(size_t)x.j * p + x.kn] : T(0);
-        x.s_in = x.last ? S[(size_t)i * p + x.kn] : T(0);
-    }
-}
-
-}  // namespace
-
-// End of one lambda of a path: apply every pending row update to the stored
-// W block, then write this workgroup's block of the dense Omega (rows
-// i = a (mod Gr), columns of slice b) and add its share of |E-hat| and of the
-// objective F(Omega) = -sum log omega_ii + 1/2 sum_ij omega_ij W_ij
-// + lam sum_{i<j} |omega_ij| to the lambda's record.
-template <typename T, bool WLDS, int RPT, int CPL>
-__device__ void end_of_lambda(const SweepParams<T> &P, int l, T lam, const Circle &C, int a,
-                              int Gr, int nr, int NR, int D, int c0, int nc, int *np, int *flist,
-                              int *ncount, const int *pj, const T *pdl, bool (&flushed)[RPT],
-                              T *wblk, const T *omp, const T *omdp, double *dred,
-                              unsigned long long *nred)
-{
-    const int tid = threadIdx.x, nthr = blockDim.x, p = P.p;
-    __syncthreads();
-    if (tid == 0)
-        *ncount = 0;
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < RPT; ++u) {
-        const int k = tid + u * nthr;
-        if (k < nr) {
-            if (flushed[u]) {
-                np[k] = 0;
-                flushed[u] = false;
-            }
-            if (np[k] > 0)
-                flist[atomicAdd(ncount, 1)] = k;
-        }
-    }
-    __syncthreads();
-    flush_rows<T, WLDS, CPL>(flist, *ncount, pj, pdl, np, D, a, Gr, p, c0, nc, P.S, P.W, wblk);
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < RPT; ++u) {
-        const int k = tid + u * nthr;
-        if (k < nr)
-            np[k] = 0;
-    }
-    T *om = P.omega_out[l];
-    double part = 0.0;
-    unsigned long long cnt = 0;
-    for (long e = tid; e < (long)nr * nc; e += nthr) {
-        const int k = (int)(e / nc), c = (int)(e - (long)k * nc);
-        const int i = a + k * Gr, j = c0 + c;
-        const T wij = WLDS ? wblk[(size_t)k * nc + c] : P.W[(size_t)i * p + j];
-        T w;
-        if (i == j) {
-            w = omdp[k];
-            part -= log((double)w);
-        } else {
-            w = omp[(size_t)C.colour(i, j) * NR + k];
-            if (i < j) {
-                part += (double)lam * fabs((double)w);
-                cnt += (w != T(0)) ? 1ull : 0ull;
-            }
-        }
-        part += 0.5 * (double)w * (double)wij;
-        om[(size_t)i * p + j] = w;
-    }
-    for (int off = 32; off > 0; off >>= 1) {
-        part += __shfl_xor(part, off, 64);
-        cnt += __shfl_xor(cnt, off, 64);
-    }
-    const int wv = tid >> 6, nw = nthr >> 6;
-    if ((tid & 63) == 0) {
-        dred[wv] = part;
-        nred[wv] = cnt;
-    }
-    __syncthreads();
-    if (tid == 0) {
-        double sp = 0.0;
-        unsigned long long sc = 0;
-        for (int w2 = 0; w2 < nw; ++w2) {
-            sp += dred[w2];
-            sc += nred[w2];
-        }
-        atomicAdd(&P.rec[l].objective, sp);
-        atomicAdd(&P.rec[l].nnz_upper, sc);
-    }
-    __syncthreads();
-}
-
-// One solve (a whole lambda path) by workgroup g of the G workgroups that
-// share the problem described by P.  CPL: columns per lane in row rewrites.
-//
-// ADJ selects the adjoint system of the implicit gradient instead of the
-// estimate.  At Omega-hat the stationarity conditions on the free entries
-// (the diagonal, and the pairs with omega_ij != 0) have the symmetric Jacobian
-//   (J v)_ij = U_ij + U_ji,   (J v)_ii = U_ii + v_ii / omega_ii^2,   U = V S,
-// with V the symmetric matrix of the unknowns v (0 off the free pairs): the
-// same structure as eqs. (2)-(3) with U in place of W.  Gauss-Seidel on
-// J v = g in the colour order is therefore this same sweep with linear
-// coordinate updates,
-//   v_ij <- (g_ij - (U_ij + U_ji - (S_ii + S_jj) v_ij)) / (S_ii + S_jj),
-//   v_ii <- (g_ii - (U_ii - S_ii v_ii)) / (S_ii + 1 / omega_ii^2),
-// a pair outside the active set keeping v_ij = 0; pairs of one colour share
-// no vertex, so they are independent as in Lemma 2.  The buffers W, omp and
-// omdp then hold U and v; P.adj_g holds g_ij per colour in omp's layout (NaN
-// for a pair that is not free) and P.adj_gd / P.adj_hd hold g_ii and
-// S_ii + 1/omega_ii^2 per row.
-template <typename T, bool WLDS, int RPT, int CPL, bool ADJ, bool TAB>
-__device__ void pcd_solve(const SweepParams<T> &P, int g, int G, unsigned char *smem_raw)
-{
-    using U = typename Sentinel<T>::U;
-    constexpr U SENT = Sentinel<T>::bits;
-    const Circle C = Circle::make(P.p);
-    // colours per sweep: p_even - 1 for Algorithm 1's schedule, or those of
-    // the given colouring (P.part[r * p + i] = partner of i in colour r, -1 idle)
-    const int p = P.p, m = TAB ? P.m_tab : C.m;
-    const int tid = threadIdx.x, nthr = blockDim.x;
-    const int a = g / P.Gc, b = g % P.Gc;
-    const int Gr = P.Gr;
-    const int nr = (a < p) ? (p - a + Gr - 1) / Gr : 0;
-    const int c0 = slice_lo(b, P.Gc, p), c1 = slice_lo(b + 1, P.Gc, p);
-    const int nc = c1 - c0;
-    const int NR = P.nr_max, D = P.depth;
-    const int PS = Gr * NR;  // published slots per colour; row i sits at (i mod Gr) * NR + i / Gr
-
-    // LDS carve-up (sizes fixed by the host in sweep_lds_bytes).
-    T *pdl = reinterpret_cast<T *>(smem_raw);   // pending changes, NR x D
-    T *wred = pdl + (size_t)NR * D;             // 16 wave partials
-    T *wblk = wred + 16;                        // W block (LDS variant): NR x nc_max
-    int *pj = reinterpret_cast<int *>(wblk + (WLDS ? (size_t)NR * P.nc_max : 0));  // NR x D sources
-    int *np = pj + (size_t)NR * D;              // pending count per row
-    int *flist = np + NR;                       // rows to rewrite this step
-    int *nflush = flist + NR;                   // [3] counters, by step mod 3; [3] spare
-    int *s_fail = nflush + 4;
-    unsigned *ured = reinterpret_cast<unsigned *>(s_fail + 1);  // 16 wave partials
-    double *dred = reinterpret_cast<double *>(((uintptr_t)(ured + 16) + 7) & ~(uintptr_t)7);
-    unsigned long long *nred = reinterpret_cast<unsigned long long *>(dred + 16);
-
-    const T *__restrict__ S = P.S;
-    const T *__restrict__ sd = P.sd;
-    T *__restrict__ Wg = P.W;
-    T *__restrict__ omp = P.omp + (size_t)g * m * NR;
-    T *__restrict__ omdp = P.omdp + (size_t)g * NR;
-    const T *__restrict__ adjg = ADJ ? P.adj_g + (size_t)g * m * NR : nullptr;
-
-    for (int k = tid; k < NR; k += nthr)
-        np[k] = 0;
-    if (tid == 0) {
-        nflush[0] = 0;
-        nflush[1] = 0;
-        nflush[2] = 0;
-        nflush[3] = 0;
-        *s_fail = 0;
-    }
-    if (WLDS) {
-        for (long e = tid; e < (long)nr * nc; e += nthr) {
-            const int k = (int)(e / nc), c = (int)(e - (long)k * nc);
-            wblk[(size_t)k * nc + c] = Wg[(size_t)(a + k * Gr) * p + c0 + c];
-        }
-    }
-    __syncthreads();
-
-    T dloc = T(0), gloc = T(0);
-    unsigned moved = 0, moved_d = 0;  // pairs / diagonals that changed (counted once each)
-    int t = 0, converged = 0, failed = 0;
-    bool flushed[RPT];
-    RowNext<T> nx[RPT];
-#pragma unroll
-    for (int u = 0; u < RPT; ++u) {
-        flushed[u] = false;
-        const int k = tid + u * nthr;
-        if (k < nr)
-            load_next<T, WLDS, TAB>(nx[u], C, P.part, m, 0, a + k * Gr, k, 0, pj, D, NR, p, c0,
-                                    c1, nc, S, Wg, wblk, omp, omdp, adjg);
-    }
-    // adjoint mode: the diagonal right-hand side and denominator of each row
-    T adj_gd[RPT], adj_hd[RPT];
-#pragma unroll
-    for (int u = 0; u < RPT; ++u) {
-        const int k = tid + u * nthr;
-        adj_gd[u] = (ADJ && k < nr) ? P.adj_gd[(size_t)g * NR + k] : T(0);
-        adj_hd[u] = (ADJ && k < nr) ? P.adj_hd[(size_t)g * NR + k] : T(1);
-    }
-    unsigned step = 0;
-
-    // A set-up kernel that found bad input leaves its bits in out[4]; then
-    // every workgroup skips the sweeps (the same word is read by all).
-    const bool run = ld_dev(&P.out[4]) == 0;
-
-    // Lambda path: lambda l runs until its own convergence test passes or
-    // maxit sweeps, then the next starts from where it stopped (warm start:
-    // Omega, W and the published entries carry over unchanged).
-    const int L = P.L > 0 ? P.L : 1;
-    int lidx = 0, tl = 0;
-    T lam = P.lams ? (T)P.lams[0] : P.lam;
-    if (P.rec && g == 0 && tid == 0)
-        P.rec[0].clock_start = __builtin_amdgcn_s_memrealtime();
-
-    while (run) {
-        const int cur = t & 1, nxt = cur ^ 1;
-        if (t >= 1) {
-            // Reset to the sentinel the slots that sweep t + 1 reads after
-            // they are written within that sweep: colours >= 1 of buffer nxt,
-            // and pd[nxt] when the diagonal entry is published in-sweep (m >= 2).
-            // Their last readers finished in sweep t - 1.
-            const long long E = (long long)(m - 1) * PS + (m >= 2 ? PS : 0);
-            const long long e0 = E * g / G, e1 = E * (g + 1) / G;
-            U *pcb = reinterpret_cast<U *>(P.pc + ((size_t)nxt * m + 1) * PS);
-            U *pdb = reinterpret_cast<U *>(P.pd + (size_t)nxt * PS);
-            for (long long e = e0 + tid; e < e1; e += nthr) {
-                if (e < (long long)(m - 1) * PS)
-                    st_dev(&pcb[e], SENT);
-                else
-                    st_dev(&pdb[e - (long long)(m - 1) * PS], SENT);
-            }
-        }
-
-        for (int r = 0; r < m && !failed; ++r) {
-            const bool last = (r == m - 1);
-            const int rn = last ? 0 : r + 1;
-            const int bufn = last ? nxt : cur;   // buffer of the next colour step
-            const int s3 = (int)(step % 3u);
-            const U *pcu = reinterpret_cast<const U *>(P.pc + ((size_t)cur * m + r) * PS);
-            const U *pdu = reinterpret_cast<const U *>(P.pd + (size_t)cur * PS);
-            T *pcn = P.pc + ((size_t)bufn * m + rn) * PS;
-            // The next step reads pd when it is the last colour; the buffer
-            // is that step's sweep.
-            T *pdn = P.pd + (size_t)(last ? nxt : cur) * PS;
-            int lfail = 0, marked = 0;
-            // optional per-step timestamps (100 MHz clock): start, rows done, rewrites done
-            unsigned long long *ts =
-                (P.tstamp && tid == 0 && step < (unsigned)P.tstamp_steps)
-                    ? P.tstamp + ((size_t)g * P.tstamp_steps + step) * 3
-                    : nullptr;
-            if (ts)
-                ts[0] = __builtin_amdgcn_s_memrealtime();
-
-#pragma unroll
-            for (int u = 0; u < RPT; ++u) {
-                const int k = tid + u * nthr;
-                if (k >= nr || lfail)
-                    continue;
-                const int i = a + k * Gr;
-                const RowNext<T> &x = nx[u];
-                const int j = x.j;
-
-                // ---- stored entries plus pending updates, for what this step publishes
-                T vpre = T(0), vdpre = T(0);
-                if (x.kn >= 0) {
-                    vpre = x.wb;
-#pragma unroll
-                    for (int e = 0; e < kMaxDepth; ++e)
-                        if (e < x.n)
-                            vpre = fma(pdl[k * D + e], x.sv[e], vpre);
-                }
-                // ---- wait for the published numerator entries of this colour
-                U blo = 0, bhi = 0, bd = 0;
-                {
-                    // slots of row i (own, contiguous over k) and of its partner
-                    const int si = a * NR + k;
-                    const int sj = (j >= 0) ? (j % Gr) * NR + j / Gr : 0;
-                    const int lo = (j >= 0 && j < i) ? sj : si, hi = (j >= 0 && j < i) ? si : sj;
-                    const bool poll_d = last && m >= 2;
-                    long long spins = 0;
-                    for (;;) {
-                        bool ok = true;
-                        if (j >= 0) {
-                            blo = ld_dev(&pcu[lo]);
-                            bhi = ld_dev(&pcu[hi]);
-                            ok = (blo != SENT) && (bhi != SENT);
-                        }
-                        if (last) {
-                            bd = ld_dev(&pdu[si]);
-                            ok = ok && (!poll_d || bd != SENT);
-                        }
-                        if (ok)
-                            break;
-                        ++spins;
-                        if (spins > P.spin_limit ||
-                            ((spins & 255) == 0 && ld_dev(&P.out[3]) != 0)) {
-                            st_dev(&P.out[3], 1);
-                            lfail = 1;
-                            break;
-                        }
-                        __builtin_amdgcn_s_sleep(1);
-                    }
-                }
-                if (lfail) {
-                    *s_fail = 1;
-                    continue;
-                }
-
-                // ---- a row rewritten last step starts a new pending list.  The
-                // once-per-sweep W_ii read comes after the wait: a load issued
-                // before the poll would hold up the poll's first answer (a
-                // wave's loads complete in order).
-                if (flushed[u]) {
-                    np[k] = 0;
-                    flushed[u] = false;
-                }
-                const int n0 = np[k];
-                if (x.pubd) {
-                    vdpre = WLDS ? wblk[(size_t)k * nc + (i - c0)] : Wg[(size_t)i * p + i];
-                    for (int e = 0; e < n0; ++e)
-                        vdpre = fma(pdl[k * D + e], S[(size_t)pj[k * D + e] * p + i], vdpre);
-                }
-
-                // ---- eq. (3) for the pair, eq. (2) after the last colour
-                T del = T(0), dd = T(0);
-                if (j >= 0) {
-                    const int lo = j < i ? j : i, hi = j < i ? i : j;
-                    const T sden = sd[lo] + sd[hi];
-                    const T bnum = fma(-sden, x.w, as_value<T>(blo) + as_value<T>(bhi));
-                    T wn;
-                    if (ADJ)
-                        wn = (x.g == x.g) ? (x.g - bnum) / sden : x.w;
-                    else
-                        wn = soft_threshold(-bnum, lam) / sden;
-                    del = wn - x.w;
-                    if (del != T(0))
-                        omp[(size_t)r * NR + k] = wn;
-                }
-                if (last) {
-                    T wii = as_value<T>(bd);
-                    if (del != T(0))
-                        wii = fma(del, x.s_ji, wii);
-                    const T sii = sd[i];
-                    const T c = fma(-sii, x.od, wii);
-                    T on;
-                    if (ADJ) {
-                        on = (adj_gd[u] - c) / adj_hd[u];
-                    } else {
-                        const T disc = sqrt(fma(c, c, T(4) * sii));
-                        // eq. (2); for c >= 0 the same root is 2 / (c + disc) without cancellation.
-                        on = (c >= T(0)) ? T(2) / (c + disc) : (disc - c) / (T(2) * sii);
-                    }
-                    dd = on - x.od;
-                    if (dd != T(0))
-                        omdp[k] = on;
-                    const T gv = ADJ ? fabs(on) : on;
-                    gloc = (gv > gloc || gv != gv) ? gv : gloc;
-                }
-
-                // ---- record the changes as pending updates of row i
-                int n = n0;
-                if (del != T(0)) {
-                    pj[k * D + n] = j;
-                    pdl[k * D + n] = del;
-                    ++n;
-                }
-                if (dd != T(0)) {
-                    pj[k * D + n] = i;
-                    pdl[k * D + n] = dd;
-                    ++n;
-                }
-                np[k] = n;
-
-                // ---- publish what the next colour reads from row i
-                if (x.kn >= 0) {
-                    T v = vpre;
-                    if (del != T(0))
-                        v = fma(del, x.s_jn, v);
-                    if (dd != T(0))
-                        v = fma(dd, x.s_in, v);
-                    st_dev(&pcn[a * NR + k], v);
-                }
-                if (x.pubd) {
-                    T v = vdpre;
-                    if (del != T(0))
-                        v = fma(del, x.s_ji, v);
-                    if (dd != T(0))
-                        v = fma(dd, sd[i], v);
-                    st_dev(&pdn[a * NR + k], v);
-                }
-                if (n > D - 2) {
-                    flist[atomicAdd(&nflush[s3], 1)] = k;
-                    flushed[u] = true;
-                    marked = 1;
-                }
-                const T ad = fabs(del) > fabs(dd) ? fabs(del) : fabs(dd);
-                dloc = (ad > dloc || ad != ad) ? ad : dloc;
-                if (b == 0) {
-                    moved += (j > i && del != T(0)) ? 1u : 0u;
-                    moved_d += (dd != T(0)) ? 1u : 0u;
-                }
-
-                // ---- operands of the row's next step.  The stored W entry is
-                // read before this step's rewrites (they start after the
-                // workgroup barrier below), so it is folded with all n entries.
-                load_next<T, WLDS, TAB>(nx[u], C, P.part, m, rn, i, k, n, pj, D, NR, p, c0, c1,
-                                        nc, S, Wg, wblk, omp, omdp, adjg);
-            }
-
-            // ---- every row of the step is done; rewrite the rows whose lists are full
-            const int any = __syncthreads_or(lfail | marked);
-            if (tid == 0)
-                nflush[(s3 + 2) % 3] = 0;  // counter of the previous step, read by all by now
-            if (ts)
-                ts[1] = __builtin_amdgcn_s_memrealtime();
-            if (any) {
-                if (*s_fail) {
-                    failed = 1;
-                    break;
-                }
-                const int nf = nflush[s3];
-                if (nf > 0) {
-                    flush_rows<T, WLDS, CPL>(flist, nf, pj, pdl, np, D, a, Gr, p, c0, nc, S, Wg, wblk);
-                    __syncthreads();
-                }
-            }
-            if (ts)
-                ts[2] = __builtin_amdgcn_s_memrealtime();
-            ++step;
-        }
-        if (failed)
-            break;
-
-        // ---- end of sweep t: reductions, then the sweep barrier
-        const T dm = block_max(dloc, wred);
-        const T gm = block_max(gloc, wred);
-        const unsigned mv = block_sum(moved, ured);
-        const unsigned mvd = block_sum(moved_d, ured);
-        if (tid == 0) {
-            unsigned long long *rt = P.red + 4 * (size_t)t;
-            __hip_atomic_fetch_max(&rt[0], ord_bits(dm), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_fetch_max(&rt[1], ord_bits(gm), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (mv)
-                __hip_atomic_fetch_add(&rt[2], (unsigned long long)mv, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-            if (mvd)
-                __hip_atomic_fetch_add(&rt[3], (unsigned long long)mvd, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-        }
-        dloc = T(0);
-        gloc = T(0);
-        moved = 0;
-        moved_d = 0;
-        if (!sweep_barrier(P, (unsigned)(t + 1), s_fail, g, G)) {
-            failed = 1;
-            break;
-        }
-        const T delta = from_ord(ld_dev(&P.red[4 * (size_t)t]), T(0));
-        const T gmax = from_ord(ld_dev(&P.red[4 * (size_t)t + 1]), T(0));
-        ++t;
-        ++tl;
-        T tol_eff = P.tol_coef * gmax;
-        tol_eff = tol_eff > P.tol ? tol_eff : P.tol;
-        const bool conv = delta < tol_eff;
-        if (conv || tl >= P.maxit) {
-            converged = conv ? 1 : 0;
-            if (P.omega_out)
-                end_of_lambda<T, WLDS, RPT, CPL>(P, lidx, lam, C, a, Gr, nr, NR, D, c0, nc, np, flist,
-                                            &nflush[3], pj, pdl, flushed, wblk, omp, omdp, dred,
-                                            nred);
-            if (P.rec && g == 0 && tid == 0) {
-                const unsigned long long now = __builtin_amdgcn_s_memrealtime();
-                P.rec[lidx].t_end = t;
-                P.rec[lidx].converged = converged;
-                P.rec[lidx].clock_end = now;
-                if (lidx + 1 < L)
-                    P.rec[lidx + 1].clock_start = now;
-            }
-            if (++lidx >= L)
-                break;
-            lam = (T)P.lams[lidx];
-            tl = 0;
-        }
-    }
-
-    // Apply every pending update so that the stored W is Omega S again.
-    __syncthreads();
-    if (tid == 0)
-        nflush[3] = 0;
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < RPT; ++u) {
-        const int k = tid + u * nthr;
-        if (k < nr) {
-            if (flushed[u])
-                np[k] = 0;
-            if (np[k] > 0)
-                flist[atomicAdd(&nflush[3], 1)] = k;
-        }
-    }
-    __syncthreads();
-    flush_rows<T, WLDS, CPL>(flist, nflush[3], pj, pdl, np, D, a, Gr, p, c0, nc, S, Wg, wblk);
-    __syncthreads();
-    if (WLDS) {
-        for (long e = tid; e < (long)nr * nc; e += nthr) {
-            const int k = (int)(e / nc), c = (int)(e - (long)k * nc);
-            Wg[(size_t)(a + k * Gr) * p + c0 + c] = wblk[(size_t)k * nc + c];
-        }
-    }
-    if (g == 0 && tid == 0) {
-        P.out[0] = t;
-        P.out[1] = converged;
-        P.out[2] = failed;
-    }
-}
 
 template <typename T>
 size_t sweep_lds_bytes(const SweepParams<T> &P)
@@ -738,7 +20,7 @@ template <typename T, bool WLDS, int RPT, bool ADJ, bool TAB>
 __global__ void __launch_bounds__(512) pcd_sweep_kernel(SweepParams<T> P)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    pcd_solve<T, WLDS, RPT, 2, ADJ, TAB>(P, blockIdx.x, gridDim.x, smem_raw);
+    pcd_solve<T, WLDS, RPT, 2, ADJ, TAB, false>(P, blockIdx.x, gridDim.x, smem_raw);
 }
 
 // Many independent problems in one launch: workgroup blockIdx.x serves
@@ -755,7 +37,7 @@ __global__ void __launch_bounds__(512)
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const SweepParams<T> P = descs[wg_problem[blockIdx.x]];
     const int g = (int)blockIdx.x - P.g0, G = P.Gr * P.Gc;
-    pcd_solve<T, false, 2, 4, false, false>(P, g, G, smem_raw);
+    pcd_solve<T, false, 2, 4, false, false, false>(P, g, G, smem_raw);
 }
 
 namespace {

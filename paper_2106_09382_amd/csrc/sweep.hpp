@@ -86,6 +86,20 @@ struct SweepParams {
     const T *adj_g;
     const T *adj_gd;
     const T *adj_hd;
+    // Joint estimation of two populations (Section 6; null/0 otherwise): this
+    // solve is population `pop` of two run in one launch with the same shape,
+    // sharing flags, red and out.  jo_S, jo_sd, jo_pc and jo_pd are the other
+    // population's S, diag(S) and published entries; jo_omp and jo_omdp hold
+    // this population's workgroups' copies of the other omega (laid out like
+    // omp and omdp); lam2 weighs the fused penalty.
+    const T *jo_S;
+    const T *jo_sd;
+    const T *jo_pc;
+    const T *jo_pd;
+    T *jo_omp;
+    T *jo_omdp;
+    T lam2;
+    int pop;
 };
 
 // Column slice b of Gc over p columns: [slice_lo(b), slice_lo(b + 1)).
@@ -117,5 +131,11 @@ hipError_t launch_sweep(const SweepParams<T> &P, int threads, hipStream_t stream
 template <typename T>
 hipError_t launch_sweep_batched(const SweepParams<T> *descs, const int *wg_problem, int G,
                                 size_t lds, int threads, hipStream_t stream);
+
+// Joint estimation: one cooperative launch of 2 G workgroups, population 0 on
+// the first G (P0) and population 1 on the rest (P1); G = Gr * Gc of both.
+template <typename T>
+hipError_t launch_sweep_joint(const SweepParams<T> &P0, const SweepParams<T> &P1, int threads,
+                              hipStream_t stream);
 
 }  // namespace concord

@@ -135,3 +135,67 @@ def test_autotune_plan_deals_by_work():
     assert sum(autotune.plan_from_infos(ps, infos, 40)) <= 40
     with pytest.raises(ValueError):
         autotune.plan([5000] * 10, [1.0] * 10, 12)
+
+
+def _fit_joint(lib, opts=None, **kw):
+    from paper_2106_09382_amd import _lib
+    vp = ctypes.c_void_p
+    a = dict(kind=0, X1=vp(0x1000), X2=vp(0x3000), n1=0, n2=0, p=8, lam1=0.1, lam2=0.05,
+             tol=1e-6, maxit=10, dt=1, o01=None, o02=None, o1=vp(0x2000), o2=vp(0x4000))
+    a.update(kw)
+    info = _lib.ConcordJointInfo()
+    rc = lib.concord_fit_joint_ex(a["kind"], a["X1"], a["X2"], a["n1"], a["n2"], a["p"],
+                                  a["lam1"], a["lam2"], a["tol"], a["maxit"], a["dt"], a["o01"],
+                                  a["o02"], a["o1"], a["o2"], ctypes.byref(info), None,
+                                  ctypes.byref(opts) if opts is not None else None)
+    return rc, info
+
+
+@pytest.mark.parametrize("kw", [
+    dict(X1=None), dict(X2=None), dict(o1=None), dict(o2=None), dict(o2=ctypes.c_void_p(0x2000)),
+    dict(p=0), dict(p=50000), dict(lam1=-0.1), dict(lam2=-0.1), dict(lam2=float("nan")),
+    dict(lam2=float("inf")), dict(tol=0.0), dict(maxit=0), dict(dt=4), dict(kind=3),
+    dict(kind=1, n1=10, n2=0),
+])
+def test_joint_invalid_arguments_return_einval(lib, kw):
+    rc, info = _fit_joint(lib, **kw)
+    assert rc == -1 and info.status == -1
+
+
+@pytest.mark.parametrize("field", ["active_set", "w_out", "device_timestamps"])
+def test_joint_rejects_single_solve_options(lib, field):
+    from paper_2106_09382_amd import _lib
+    opts = _lib.ConcordOptions()
+    setattr(opts, field, 1)
+    rc, _ = _fit_joint(lib, opts=opts)
+    assert rc == -1
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The ctypes structures have the C header's sizes and field offsets
+    (a small C program compiled with gcc prints them)."""
+    from paper_2106_09382_amd import _lib
+    structs = {"concord_info": _lib.ConcordInfo, "concord_joint_info": _lib.ConcordJointInfo,
+               "concord_options": _lib.ConcordOptions,
+               "concord_batch_options": _lib.ConcordBatchOptions}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "concord.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    import subprocess
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o",
+                    str(exe)], check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], capture_output=True, text=True,
+                               check=True).stdout.splitlines():
+        c, f, v = line.split()
+        got[(c, f)] = int(v)
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)

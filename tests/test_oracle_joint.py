@@ -204,3 +204,19 @@ def test_delta_is_the_largest_change_over_both_matrices():
         pop2_larger |= d2 > d1
         prev = (O1, O2)
     assert pop2_larger
+
+
+def test_block_update_at_a_fixed_point():
+    # at the oracle's converged point every block update is (nearly) the identity
+    S1, S2 = _pair_of_grams(20, 50, 7)
+    O1, O2, info, _ = joint.pcd(S1, S2, 0.1, 0.03, 1e-14, 20000)
+    assert info["converged"]
+    worst = 0.0
+    for i in range(20):
+        for j in range(i, 20):
+            x1, x2 = joint.block_update_at(S1, S2, O1, O2, i, j, 0.1, 0.03)
+            worst = max(worst, abs(x1 - O1[i, j]), abs(x2 - O2[i, j]))
+    assert worst < 1e-12
+    # and away from it, not
+    x1, _ = joint.block_update_at(S1, S2, np.eye(20), np.eye(20), 0, 0, 0.1, 0.03)
+    assert abs(x1 - 1.0) > 1e-3
