@@ -423,7 +423,19 @@ def main() -> int:
     ap.add_argument("--dump-y", metavar="PATH",
                     help="write the workload's Y (raw float64, n x p) to PATH and exit; "
                          "input for the native driver concord_bench")
+    ap.add_argument("--dump-joint-y", metavar="PREFIX",
+                    help="write the joint workload's Y_1 and Y_2 (raw float64, 2000 x 5000) to "
+                         "PREFIX1.bin and PREFIX2.bin and exit")
     args = ap.parse_args()
+
+    if args.dump_joint_y:
+        from paper_2106_09382_amd import datagen
+        jp = datagen.joint_problem(0)
+        for m in (0, 1):
+            jp["y"][m].astype("<f8").tofile(f"{args.dump_joint_y}{m + 1}.bin")
+        log(f"bench: wrote Y_1, Y_2 ({jp['n']} x {jp['p']}, seed {jp['seed']}) to "
+            f"{args.dump_joint_y}{{1,2}}.bin")
+        return 0
 
     if args.dump_y:
         from paper_2106_09382_amd import datagen
