@@ -78,6 +78,9 @@ CASES = [
     (130, 90, 0.15, 0.03, 7, dict(row_groups=5, col_slices=3)),
     (130, 90, 0.15, 0.03, 7, dict(row_groups=4, col_slices=2, w_in_lds=2, pending_depth=3)),
     (211, 300, 0.1, 0.02, 8, dict(row_groups=16, col_slices=4, block_threads=64)),
+    # two rows per thread, W in HBM and in LDS
+    (300, 150, 0.15, 0.05, 16, dict(row_groups=2, col_slices=2, block_threads=128, w_in_lds=2)),
+    (160, 200, 0.1, 0.03, 17, dict(row_groups=2, col_slices=2, block_threads=64, w_in_lds=1)),
     (301, 150, 0.2, 0.1, 9, {}),
 ]
 
