@@ -67,13 +67,12 @@ def sweep_bytes(p: int, elem: int, sweeps: int, moved_pairs: int, moved_diag: in
     return float(elem) * (1.5 * p * m * sweeps + 6.0 * p * moved_pairs + 3.0 * p * moved_diag)
 
 
-def cpu_oracle_baseline(y, p: int, lam: float, elem: int, gpu_sweeps: int, bytes_per_sweep: float,
+def cpu_oracle_baseline(S, p: int, lam: float, elem: int, gpu_sweeps: int, bytes_per_sweep: float,
                         budget_s: float) -> dict:
     """Time the CPU oracle (serial, FP64, direct sums) on a bounded sample:
     the first c colour steps of sweep 1, extrapolated to one sweep."""
     import oracle
 
-    S = oracle.gram(y)
     m = p + (p & 1) - 1
     t0 = time.perf_counter()
     oracle.pcd(S, lam, 1e-300, 1, colour_limit=2)
@@ -95,6 +94,39 @@ def cpu_oracle_baseline(y, p: int, lam: float, elem: int, gpu_sweeps: int, bytes
         "host_cpu": _cpu_model(),
         "host_threads": os.cpu_count(),
     }
+
+
+def cpu_wform_baseline(S, p: int, lam: float, gpu_bytes: float, budget_s: float) -> dict:
+    """Time the CPU baseline with a maintained W (FP64): the whole first sweep
+    on all host threads, and a bounded sample of sweep 1 on one thread.  Each
+    rate is algorithmic bytes / time; time to tolerance is extrapolated as
+    the GPU solve's algorithmic bytes / that rate."""
+    from oracle import cpu_baseline
+
+    m = p + (p & 1) - 1
+    t0 = time.perf_counter()
+    _, info = cpu_baseline.pcd_wform(S, lam, 1e-300, 1)
+    dt = time.perf_counter() - t0
+    b = sweep_bytes(p, 8, 1, info["moved_pairs"], info["moved_diag"])
+    par = {"GBps": b / dt / 1e9, "cores": info["threads"], "t_sweep1_s": dt,
+           "time_to_tol_s_extrapolated": gpu_bytes / (b / dt),
+           "sample": f"sweep 1 ({info['moved_pairs']} pair changes), OpenMP over a colour's pairs"}
+    # per-colour cost from the difference of two runs (each also copies S into W)
+    t0 = time.perf_counter()
+    cpu_baseline.pcd_wform(S, lam, 1e-300, 1, threads=1, colour_limit=2)
+    t1 = time.perf_counter()
+    cpu_baseline.pcd_wform(S, lam, 1e-300, 1, threads=1, colour_limit=42)
+    per = max(time.perf_counter() - t1 - (t1 - t0), 1e-6) / 40
+    c = int(max(2, min(m, budget_s / per)))
+    t0 = time.perf_counter()
+    _, info = cpu_baseline.pcd_wform(S, lam, 1e-300, 1, threads=1, colour_limit=c)
+    dt = time.perf_counter() - t0
+    b = float(8) * (1.5 * p * c + 6.0 * p * info["moved_pairs"])
+    ser = {"GBps": b / dt / 1e9, "cores": 1, "time_to_tol_s_extrapolated": gpu_bytes / (b / dt),
+           "sample": f"first {c} of {m} colour steps of sweep 1 ({dt:.1f} s)"}
+    return {"kind": "Algorithm 1 with a maintained W = Omega S, FP64 (oracle/cpu_pcd.c)",
+            "parallel": par, "serial": ser, "host_cpu": _cpu_model(),
+            "host_threads": os.cpu_count()}
 
 
 def measured_traffic(p: int, n: int, lam: float, dtype: str):
@@ -248,6 +280,34 @@ def active_measurement(Y, tol: float, shape: dict) -> dict:
                          "code": best["code"]}
         row["speedup"] = row["plain"]["ms"] / row["active"]["ms"]
         out[f"lambda_{lam}"] = row
+    return out
+
+
+def chain_measurement(p: int, n: int, tol: float, shape: dict) -> dict:
+    """The chain-graph workload at the same size (omega_ii = 1, omega_{i,i+1} =
+    0.4), FP64 from Y: time to tolerance and algorithmic bandwidth."""
+    import torch
+
+    from paper_2106_09382_amd import _lib, datagen
+
+    pr = datagen.problem(3, graph="chain", p=p, n=n)
+    Y = torch.tensor(pr["y"], device="cuda")
+    m = p + (p & 1) - 1
+    out = {"workload": f"chain Omega0, p={p}, n={n}, tol={tol}, f64, from Y"}
+    for lam in (0.1, 0.2):
+        best = None
+        for _ in range(2):
+            _, info = _lib.fit(Y, lam, tol, 500, kind="Y", check=False, **shape)
+            torch.cuda.synchronize()
+            if best is None or info["sweep_ms"] < best["sweep_ms"]:
+                best = info
+        b = sweep_bytes(p, 8, best["sweeps"], best["moved_pairs"], best["moved_diag"])
+        gbs = b / (best["sweep_ms"] * 1e-3) / 1e9
+        out[f"lambda_{lam}"] = {"ms": best["elapsed_ms"], "sweep_ms": best["sweep_ms"],
+                                "sweeps": best["sweeps"], "code": best["code"],
+                                "nnz_upper": best["nnz_upper"], "algorithmic_GBps": gbs,
+                                "frac_of_8TBps": gbs / 8000.0,
+                                "us_per_colour_step": best["sweep_ms"] * 1e3 / (best["sweeps"] * m)}
     return out
 
 
@@ -540,13 +600,21 @@ def main() -> int:
     }
     if not args.no_cpu_baseline:
         log(f"bench: timing the CPU oracle on a ~{args.cpu_seconds:.0f} s sample")
-        res["cpu_baseline"] = cpu_oracle_baseline(y, args.p, args.lam, elem, sweeps,
+        import oracle
+        S_cpu = oracle.gram(y)
+        res["cpu_baseline"] = cpu_oracle_baseline(S_cpu, args.p, args.lam, elem, sweeps,
                                                   bytes_launch / max(sweeps, 1), args.cpu_seconds)
+        if args.dtype == "f64":
+            log("bench: timing the CPU baseline with a maintained W")
+            res["cpu_wform"] = cpu_wform_baseline(S_cpu, args.p, args.lam, bytes_launch,
+                                                  args.cpu_seconds / 2)
     if args.p == 5000 and args.dtype == "f64":
         res["floor"] = floor_measurement(Y, shape, bytes_launch / max(sweeps, 1),
                                          float(np.mean(sweep_ms)) / max(sweeps, 1), m)
         res["fp32"] = fp32_measurement(Y, args.lam, args.tol, shape)
         res["active_set"] = active_measurement(Y, args.tol, shape)
+        if args.graph == "er":
+            res["chain"] = chain_measurement(args.p, args.n, args.tol, shape)
     if not args.no_batched:
         res["batched"] = batched_measurement(args.plain_all)
     if not args.no_backward:

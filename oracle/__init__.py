@@ -20,6 +20,9 @@ write them).  The helpers here are plain NumPy definitions:
 support, sweeps over it, full sweeps to decide convergence).
 ``oracle.backward`` holds the implicit gradient of the estimate (dL/dS and
 dL/dlam from the stationarity system on the active set, by a dense solve).
+``oracle.cpu_baseline`` is not part of the oracle: it is the benchmark's
+CPU baseline (Algorithm 1 with a maintained W = Omega S, serial or
+colour-parallel with OpenMP), pinned against the oracle in the tests.
 ``oracle.joint`` holds the joint estimation of two precision matrices with a
 fused penalty (Section 6): block coordinate descent on Algorithm 1's schedule,
 its objective and its optimality conditions.
@@ -34,15 +37,17 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "concord_oracle.c")
+_SRC_CPU = os.path.join(_HERE, "cpu_pcd.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 
 def build() -> str:
-    """Compile the C oracle with gcc into oracle/liboracle.so."""
+    """Compile the C oracle and the CPU baseline (OpenMP) with gcc into
+    oracle/liboracle.so."""
     tmp = _LIB + ".tmp"
-    subprocess.run(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"],
-                   check=True)
+    subprocess.run(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fopenmp", "-o", tmp, _SRC,
+                    _SRC_CPU, "-lm"], check=True)
     os.replace(tmp, _LIB)
     return _LIB
 
@@ -51,7 +56,8 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(os.path.getmtime(_SRC),
+                                                                 os.path.getmtime(_SRC_CPU)):
         build()
     lib = ctypes.CDLL(_LIB)
     dp = ctypes.POINTER(ctypes.c_double)
@@ -80,6 +86,9 @@ def _load():
     lib.oracle_joint_pcd.argtypes = [dp, dp, ctypes.c_int, cd_, cd_, cd_, ctypes.c_int, dp, dp,
                                      dp, dp, dp, dp]
     lib.oracle_joint_pcd.restype = ctypes.c_int
+    lib.cpu_pcd_wform.argtypes = [dp, ctypes.c_int, cd_, cd_, ctypes.c_int, ctypes.c_int,
+                                  ctypes.c_longlong, dp, dp]
+    lib.cpu_pcd_wform.restype = ctypes.c_int
     _lib = lib
     return lib
 
