@@ -228,6 +228,7 @@ def batched_measurement(plain_all: bool) -> dict:
         "sweeps_total": int(sweeps),
         "algorithmic_GBs": byt / wall / 1e9,
         "workgroups": int(sum(row[0]["row_groups"] for row in infos)),
+        "plan_workgroups": [int(x) for x in tuned],
     }
 
 
@@ -483,10 +484,28 @@ def main() -> int:
     ap.add_argument("--dump-y", metavar="PATH",
                     help="write the workload's Y (raw float64, n x p) to PATH and exit; "
                          "input for the native driver concord_bench")
+    ap.add_argument("--only", choices=["batched", "backward", "joint", "active", "chain"],
+                    help="run one side measurement alone and print its JSON (for profiling)")
+    ap.add_argument("--dump-batched", metavar="DIR",
+                    help="write the batched workload (DIR/y_<b>.bin raw float64 n_b x p_b, "
+                         "DIR/problems.txt 'p n' per line, DIR/lambdas.txt) and exit")
     ap.add_argument("--dump-joint-y", metavar="PREFIX",
                     help="write the joint workload's Y_1 and Y_2 (raw float64, 2000 x 5000) to "
                          "PREFIX1.bin and PREFIX2.bin and exit")
     args = ap.parse_args()
+
+    if args.dump_batched:
+        from paper_2106_09382_amd import datagen
+        os.makedirs(args.dump_batched, exist_ok=True)
+        probs = datagen.batched_problems(0)
+        with open(os.path.join(args.dump_batched, "problems.txt"), "w") as fh:
+            for b, q in enumerate(probs):
+                q["y"].astype("<f8").tofile(os.path.join(args.dump_batched, f"y_{b}.bin"))
+                fh.write(f"{q['p']} {q['n']}\n")
+        with open(os.path.join(args.dump_batched, "lambdas.txt"), "w") as fh:
+            fh.write("\n".join(repr(float(x)) for x in datagen.lambda_path()) + "\n")
+        log(f"bench: wrote {len(probs)} batched problems to {args.dump_batched}")
+        return 0
 
     if args.dump_joint_y:
         from paper_2106_09382_amd import datagen
@@ -502,6 +521,28 @@ def main() -> int:
         pr = datagen.problem(3, graph=args.graph, p=args.p, n=args.n)
         pr["y"].astype("<f8").tofile(args.dump_y)
         log(f"bench: wrote Y ({args.n} x {args.p}, seed {pr['seed']}) to {args.dump_y}")
+        return 0
+
+    if args.only:
+        import torch
+        if not torch.cuda.is_available():
+            log("bench.py: no GPU visible")
+            return 1
+        from paper_2106_09382_amd import _lib
+        _lib.load()
+        if args.only == "batched":
+            r = batched_measurement(args.plain_all)
+        elif args.only == "backward":
+            r = backward_measurement()
+        elif args.only == "joint":
+            r = joint_measurement()
+        elif args.only == "chain":
+            r = chain_measurement(args.p, args.n, args.tol, {})
+        else:
+            from paper_2106_09382_amd import datagen
+            pr = datagen.problem(3, graph=args.graph, p=args.p, n=args.n)
+            r = active_measurement(torch.tensor(pr["y"], device="cuda"), args.tol, {})
+        print(json.dumps({"only": args.only, args.only: r}), flush=True)
         return 0
 
     world = int(os.environ.get("WORLD_SIZE", "1"))

@@ -6,6 +6,7 @@
 //                 [--threads C] [--depth D]
 //   concord_bench --copy MIB
 //   concord_bench --y FILE --y2 FILE2 --lam2 L2 --n N --p P [...]
+//   concord_bench --batched DIR [--plan FILE] [--tol T] [--maxit K] [--reps R]
 //
 // --copy runs one device-to-device copy of MIB mebibytes (the runtime's copy
 // kernel) and exits: a reference of known size for hardware byte counters.
@@ -15,6 +16,11 @@
 // one concord_fit from Y.  One JSON line per repetition goes to stdout.
 // With --y2, each repetition is one concord_fit_joint of the two populations
 // Y (FILE) and Y2 (FILE2, also n x p) with thresholds --lam and --lam2.
+// With --batched, DIR holds problems.txt ('p n' per problem), lambdas.txt
+// and y_<b>.bin (raw float64 n x p), as bench.py --dump-batched writes them;
+// each repetition is one FP32 concord_fit_batched_ex of all problems along
+// the lambda path, with the workgroup counts of --plan FILE (one per
+// problem) or the built-in plan.
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
@@ -32,14 +38,120 @@ void usage()
     std::fprintf(stderr,
                  "usage: concord_bench --y FILE --n N --p P [--lam L] [--tol T] [--maxit K] "
                  "[--reps R] [--f32] [--row-groups A] [--col-slices B] [--threads C] "
-                 "[--depth D] [--y2 FILE2 --lam2 L2]\n       concord_bench --copy MIB\n");
+                 "[--depth D] [--y2 FILE2 --lam2 L2]\n       concord_bench --copy MIB\n"
+                 "       concord_bench --batched DIR [--plan FILE] [--tol T] [--maxit K] "
+                 "[--reps R]\n");
+}
+
+// The batched workload from DIR, FP32, one launch per repetition.
+int run_batched(const std::string &dir, const std::string &plan, double tol, int maxit, int reps)
+{
+    std::vector<int64_t> ps, ns;
+    {
+        FILE *f = std::fopen((dir + "/problems.txt").c_str(), "r");
+        long long a = 0, b = 0;
+        while (f && std::fscanf(f, "%lld %lld", &a, &b) == 2) {
+            ps.push_back(a);
+            ns.push_back(b);
+        }
+        if (f)
+            std::fclose(f);
+    }
+    std::vector<double> lams;
+    {
+        FILE *f = std::fopen((dir + "/lambdas.txt").c_str(), "r");
+        double x = 0;
+        while (f && std::fscanf(f, "%lf", &x) == 1)
+            lams.push_back(x);
+        if (f)
+            std::fclose(f);
+    }
+    const int B = (int)ps.size(), L = (int)lams.size();
+    if (B < 1 || L < 1) {
+        std::fprintf(stderr, "concord_bench: no problems or lambdas in %s\n", dir.c_str());
+        return 1;
+    }
+    std::vector<int32_t> pw;
+    if (!plan.empty()) {
+        FILE *f = std::fopen(plan.c_str(), "r");
+        int x = 0;
+        while (f && std::fscanf(f, "%d", &x) == 1)
+            pw.push_back(x);
+        if (f)
+            std::fclose(f);
+        if ((int)pw.size() != B) {
+            std::fprintf(stderr, "concord_bench: %s holds %zu counts for %d problems\n",
+                         plan.c_str(), pw.size(), B);
+            return 1;
+        }
+    }
+    std::vector<void *> dX(B, nullptr), dOm((size_t)B * L, nullptr);
+    std::vector<double> lam_all((size_t)B * L);
+    for (int b = 0; b < B; ++b) {
+        const size_t cnt = (size_t)ns[b] * ps[b];
+        std::vector<double> y(cnt);
+        const std::string file = dir + "/y_" + std::to_string(b) + ".bin";
+        FILE *f = std::fopen(file.c_str(), "rb");
+        if (!f || std::fread(y.data(), sizeof(double), cnt, f) != cnt) {
+            std::fprintf(stderr, "concord_bench: cannot read %s\n", file.c_str());
+            return 1;
+        }
+        std::fclose(f);
+        std::vector<float> y32(y.begin(), y.end());
+        if (hipMalloc(&dX[b], sizeof(float) * cnt) != hipSuccess ||
+            hipMemcpy(dX[b], y32.data(), sizeof(float) * cnt, hipMemcpyHostToDevice) !=
+                hipSuccess) {
+            std::fprintf(stderr, "concord_bench: device allocation or copy failed\n");
+            return 1;
+        }
+        for (int l = 0; l < L; ++l) {
+            if (hipMalloc(&dOm[(size_t)b * L + l], sizeof(float) * ps[b] * ps[b]) != hipSuccess) {
+                std::fprintf(stderr, "concord_bench: device allocation failed\n");
+                return 1;
+            }
+            lam_all[(size_t)b * L + l] = lams[l];
+        }
+    }
+    concord_batch_options bo;
+    std::memset(&bo, 0, sizeof(bo));
+    bo.problem_workgroups = pw.empty() ? nullptr : pw.data();
+    std::vector<concord_info> info((size_t)B * L);
+    int rc = 0;
+    for (int r = 0; r < reps; ++r) {
+        rc = concord_fit_batched_ex(B, CONCORD_INPUT_Y, dX.data(), ns.data(), ps.data(), L,
+                                    lam_all.data(), tol, maxit, CONCORD_F32, dOm.data(),
+                                    info.data(), nullptr, &bo);
+        long long sweeps = 0;
+        double dev_max = 0.0;
+        for (int b = 0; b < B; ++b) {
+            double dev = 0.0;
+            for (int l = 0; l < L; ++l) {
+                sweeps += info[(size_t)b * L + l].sweeps;
+                dev += info[(size_t)b * L + l].sweep_ms;
+            }
+            dev_max = dev > dev_max ? dev : dev_max;
+        }
+        std::printf("{\"rep\": %d, \"code\": %d, \"problems\": %d, \"lambdas\": %d, "
+                    "\"plan\": \"%s\", \"elapsed_ms\": %.3f, \"sweeps_total\": %lld, "
+                    "\"slowest_problem_ms\": %.3f}\n",
+                    r, rc, B, L, pw.empty() ? "built-in" : "file", info[0].elapsed_ms, sweeps,
+                    dev_max);
+        std::fflush(stdout);
+        if (rc < 0)
+            break;
+    }
+    for (void *x : dX)
+        (void)hipFree(x);
+    for (void *x : dOm)
+        (void)hipFree(x);
+    return rc < 0 ? 1 : 0;
 }
 
 }  // namespace
 
 int main(int argc, char **argv)
 {
-    std::string path, path2;
+    std::string path, path2, bdir, plan;
     double lam2 = 0.0;
     long long n = 0, p = 0, copy_mib = 0;
     double lam = 0.1, tol = 1e-6;
@@ -79,6 +191,10 @@ int main(int argc, char **argv)
             opt.block_threads = std::atoi(next());
         else if (a == "--depth")
             opt.pending_depth = std::atoi(next());
+        else if (a == "--batched")
+            bdir = next();
+        else if (a == "--plan")
+            plan = next();
         else if (a == "--y2")
             path2 = next();
         else if (a == "--lam2")
@@ -105,6 +221,8 @@ int main(int argc, char **argv)
         (void)hipFree(dst);
         return 0;
     }
+    if (!bdir.empty())
+        return run_batched(bdir, plan, tol, maxit, reps);
     if (path.empty() || n < 1 || p < 1 || reps < 1) {
         usage();
         return 2;
