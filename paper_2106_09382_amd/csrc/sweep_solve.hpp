@@ -409,6 +409,12 @@ __device__ void end_of_lambda(const SweepParams<T> &P, int l, T lam, const Circl
 // omdp then hold U and v; P.adj_g holds g_ij per colour in omp's layout (NaN
 // for a pair that is not free) and P.adj_gd / P.adj_hd hold g_ii and
 // S_ii + 1/omega_ii^2 per row.
+//
+// TAB takes the partners from the colouring table P.part (active-set sweeps)
+// instead of Algorithm 1's closed form.  JNT runs population P.pop of a joint
+// two-population solve (Section 6): each pair and diagonal entry is updated by
+// the block minimisers joint_pair / joint_diag from both populations' published
+// entries, and this workgroup also keeps its copy of the other omega.
 template <typename T, bool WLDS, int RPT, int CPL, bool ADJ, bool TAB, bool JNT>
 __device__ void pcd_solve(const SweepParams<T> &P, int g, int G, unsigned char *smem_raw)
 {
