@@ -514,6 +514,9 @@ def main() -> int:
                          "input for the native driver concord_bench")
     ap.add_argument("--only", choices=["batched", "backward", "joint", "active", "chain"],
                     help="run one side measurement alone and print its JSON (for profiling)")
+    ap.add_argument("--dump-config", type=int, default=3,
+                    help="workload whose Y --dump-y writes (3: the benchmark solve; 5: the "
+                         "gradient workload, p=2000 n=1000 chain)")
     ap.add_argument("--dump-batched", metavar="DIR",
                     help="write the batched workload (DIR/y_<b>.bin raw float64 n_b x p_b, "
                          "DIR/problems.txt 'p n' per line, DIR/lambdas.txt) and exit")
@@ -546,9 +549,12 @@ def main() -> int:
 
     if args.dump_y:
         from paper_2106_09382_amd import datagen
-        pr = datagen.problem(3, graph=args.graph, p=args.p, n=args.n)
+        if args.dump_config == 5:
+            pr = datagen.problem(5)
+        else:
+            pr = datagen.problem(3, graph=args.graph, p=args.p, n=args.n)
         pr["y"].astype("<f8").tofile(args.dump_y)
-        log(f"bench: wrote Y ({args.n} x {args.p}, seed {pr['seed']}) to {args.dump_y}")
+        log(f"bench: wrote Y ({pr['n']} x {pr['p']}, seed {pr['seed']}) to {args.dump_y}")
         return 0
 
     if args.only:

@@ -7,6 +7,7 @@
 //   concord_bench --copy MIB
 //   concord_bench --y FILE --y2 FILE2 --lam2 L2 --n N --p P [...]
 //   concord_bench --batched DIR [--plan FILE] [--tol T] [--maxit K] [--reps R]
+//   concord_bench --backward --y FILE --n N --p P [--lam L] [--tol T] [--reps R]
 //
 // --copy runs one device-to-device copy of MIB mebibytes (the runtime's copy
 // kernel) and exits: a reference of known size for hardware byte counters.
@@ -20,7 +21,10 @@
 // and y_<b>.bin (raw float64 n x p), as bench.py --dump-batched writes them;
 // each repetition is one FP32 concord_fit_batched_ex of all problems along
 // the lambda path, with the workgroup counts of --plan FILE (one per
-// problem) or the built-in plan.
+// problem) or the built-in plan.  With --backward, each repetition is one
+// FP64 solve from Y followed by concord_backward of
+// L = |Omega-hat - Omega_0|_F^2 with the chain Omega_0 (1 on the diagonal,
+// 0.4 beside it), the gradient workload of bench.py.
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
@@ -40,6 +44,8 @@ void usage()
                  "[--reps R] [--f32] [--row-groups A] [--col-slices B] [--threads C] "
                  "[--depth D] [--y2 FILE2 --lam2 L2]\n       concord_bench --copy MIB\n"
                  "       concord_bench --batched DIR [--plan FILE] [--tol T] [--maxit K] "
+                 "[--reps R]\n"
+                 "       concord_bench --backward --y FILE --n N --p P [--lam L] [--tol T] "
                  "[--reps R]\n");
 }
 
@@ -153,6 +159,7 @@ int main(int argc, char **argv)
 {
     std::string path, path2, bdir, plan;
     double lam2 = 0.0;
+    int backward = 0;
     long long n = 0, p = 0, copy_mib = 0;
     double lam = 0.1, tol = 1e-6;
     int maxit = 500, reps = 1, f32 = 0;
@@ -191,6 +198,8 @@ int main(int argc, char **argv)
             opt.block_threads = std::atoi(next());
         else if (a == "--depth")
             opt.pending_depth = std::atoi(next());
+        else if (a == "--backward")
+            backward = 1;
         else if (a == "--batched")
             bdir = next();
         else if (a == "--plan")
@@ -257,6 +266,53 @@ int main(int argc, char **argv)
     if (!upload(path, &dY) || hipMalloc(&dOm, esz * (size_t)p * p) != hipSuccess) {
         std::fprintf(stderr, "concord_bench: set-up failed\n");
         return 1;
+    }
+    if (backward) {
+        if (f32) {
+            std::fprintf(stderr, "concord_bench: --backward runs in FP64\n");
+            return 2;
+        }
+        const size_t pp = (size_t)p * p;
+        void *dS = nullptr, *dC = nullptr, *dG = nullptr;
+        if (hipMalloc(&dS, 8 * pp) != hipSuccess || hipMalloc(&dC, 8 * pp) != hipSuccess ||
+            hipMalloc(&dG, 8 * pp) != hipSuccess ||
+            concord_gram(dY, n, p, CONCORD_F64, dS, nullptr) != CONCORD_OK) {
+            std::fprintf(stderr, "concord_bench: set-up failed\n");
+            return 1;
+        }
+        std::vector<double> om(pp), c(pp);
+        int rc = 0;
+        for (int r = 0; r < reps; ++r) {
+            concord_info fi, bi;
+            rc = concord_fit(CONCORD_INPUT_S, dS, n, p, lam, tol, maxit, CONCORD_F64, nullptr,
+                             dOm, &fi, nullptr);
+            if (rc < 0)
+                break;
+            // C = dL/dOmega-hat = 2 (Omega-hat - Omega_0), chain Omega_0
+            if (hipMemcpy(om.data(), dOm, 8 * pp, hipMemcpyDeviceToHost) != hipSuccess)
+                return 1;
+            for (long long i = 0; i < p; ++i)
+                for (long long j = 0; j < p; ++j) {
+                    const double o0 = (i == j) ? 1.0 : ((i - j == 1 || j - i == 1) ? 0.4 : 0.0);
+                    c[(size_t)i * p + j] = 2.0 * (om[(size_t)i * p + j] - o0);
+                }
+            if (hipMemcpy(dC, c.data(), 8 * pp, hipMemcpyHostToDevice) != hipSuccess)
+                return 1;
+            double gl = 0.0;
+            rc = concord_backward(dS, dOm, p, dC, dG, &gl, tol, maxit, CONCORD_F64, &bi, nullptr);
+            std::printf("{\"rep\": %d, \"code\": %d, \"forward_ms\": %.3f, \"forward_sweeps\": %d, "
+                        "\"backward_ms\": %.3f, \"backward_sweeps\": %d, \"grad_lambda\": %.10g}\n",
+                        r, rc, fi.elapsed_ms, fi.sweeps, bi.elapsed_ms, bi.sweeps, gl);
+            std::fflush(stdout);
+            if (rc < 0)
+                break;
+        }
+        (void)hipFree(dS);
+        (void)hipFree(dC);
+        (void)hipFree(dG);
+        (void)hipFree(dY);
+        (void)hipFree(dOm);
+        return rc < 0 ? 1 : 0;
     }
     if (!path2.empty()) {
         if (!upload(path2, &dY2) || hipMalloc(&dOm2, esz * (size_t)p * p) != hipSuccess) {
