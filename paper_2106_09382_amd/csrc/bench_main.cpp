@@ -3,7 +3,7 @@
 //
 //   concord_bench --y FILE --n N --p P [--lam L] [--tol T] [--maxit K]
 //                 [--reps R] [--f32] [--row-groups A] [--col-slices B]
-//                 [--threads C] [--depth D]
+//                 [--threads C] [--depth D] [--active]
 //   concord_bench --copy MIB
 //   concord_bench --y FILE --y2 FILE2 --lam2 L2 --n N --p P [...]
 //   concord_bench --batched DIR [--plan FILE] [--tol T] [--maxit K] [--reps R]
@@ -42,7 +42,7 @@ void usage()
     std::fprintf(stderr,
                  "usage: concord_bench --y FILE --n N --p P [--lam L] [--tol T] [--maxit K] "
                  "[--reps R] [--f32] [--row-groups A] [--col-slices B] [--threads C] "
-                 "[--depth D] [--y2 FILE2 --lam2 L2]\n       concord_bench --copy MIB\n"
+                 "[--depth D] [--active] [--y2 FILE2 --lam2 L2]\n       concord_bench --copy MIB\n"
                  "       concord_bench --batched DIR [--plan FILE] [--tol T] [--maxit K] "
                  "[--reps R]\n"
                  "       concord_bench --backward --y FILE --n N --p P [--lam L] [--tol T] "
@@ -198,6 +198,8 @@ int main(int argc, char **argv)
             opt.block_threads = std::atoi(next());
         else if (a == "--depth")
             opt.pending_depth = std::atoi(next());
+        else if (a == "--active")
+            opt.active_set = 1;
         else if (a == "--backward")
             backward = 1;
         else if (a == "--batched")
@@ -353,11 +355,12 @@ int main(int argc, char **argv)
         std::printf("{\"rep\": %d, \"code\": %d, \"sweeps\": %d, \"delta\": %.6e, "
                     "\"nnz_upper\": %lld, \"elapsed_ms\": %.3f, \"gram_ms\": %.3f, "
                     "\"sweep_ms\": %.3f, \"moved_pairs\": %lld, \"moved_diag\": %lld, "
-                    "\"row_groups\": %d, \"col_slices\": %d, \"threads\": %d, \"depth\": %d}\n",
+                    "\"row_groups\": %d, \"col_slices\": %d, \"threads\": %d, \"depth\": %d, "
+                    "\"active_sweeps\": %d}\n",
                     r, rc, info.sweeps, info.delta, (long long)info.nnz_upper, info.elapsed_ms,
                     info.gram_ms, info.sweep_ms, (long long)info.moved_pairs,
                     (long long)info.moved_diag, info.row_groups, info.col_slices,
-                    info.block_threads, info.pending_depth);
+                    info.block_threads, info.pending_depth, info.active_sweeps);
         std::fflush(stdout);
         if (rc < 0)
             break;
