@@ -1,7 +1,9 @@
 // Support kernels of the active-set sweeps: the support of the current Omega
-// as an edge list (to be coloured) and the dense Omega back from the sweep
-// layout of a colour table.
+// as an edge list (to be coloured), the dense Omega back from the sweep
+// layout of a colour table, and the refresh of Algorithm 1's layout after
+// the sweeps over that table.
 #include "device_common.hpp"
+#include "schedule.hpp"
 #include "support.hpp"
 
 namespace concord {
@@ -66,7 +68,48 @@ __global__ void scatter_omega_kernel(const T *__restrict__ omp, const T *__restr
     }
 }
 
+// Algorithm 1's sweep layout after sweeps over a colouring of the support:
+// only the listed support pairs and the diagonal can have changed, so only
+// their entries are rewritten, in the copy of every column slice.  Work item
+// e < 2 ne Gc is endpoint e / Gc % 2 of edge e / (2 Gc) in slice e % Gc;
+// the next p Gc items are the diagonals.
+template <typename T>
+__global__ void refresh_layout_kernel(const T *__restrict__ omega, const int *__restrict__ edges,
+                                      int ne, int p, int Gr, int Gc, int NR,
+                                      T *__restrict__ omp, T *__restrict__ omdp)
+{
+    const Circle C = Circle::make(p);
+    const long long ne_work = 2ll * ne * Gc, total = ne_work + (long long)p * Gc;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+         e += (long long)gridDim.x * blockDim.x) {
+        if (e < ne_work) {
+            const int b = (int)(e % Gc);
+            const long long q = e / Gc;
+            const int side = (int)(q & 1);
+            const long long ed = q >> 1;
+            const int i = edges[2 * ed + side], j = edges[2 * ed + 1 - side];
+            const int a = i % Gr, k = i / Gr, g = a * Gc + b;
+            omp[((size_t)g * C.m + C.colour(i, j)) * NR + k] = omega[(size_t)i * p + j];
+        } else {
+            const long long d = e - ne_work;
+            const int b = (int)(d % Gc), i = (int)(d / Gc);
+            const int a = i % Gr, k = i / Gr, g = a * Gc + b;
+            omdp[(size_t)g * NR + k] = omega[(size_t)i * p + i];
+        }
+    }
+}
+
 }  // namespace
+
+template <typename T>
+hipError_t launch_refresh_layout(const T *omega, const int *edges, int ne, int p, int Gr, int Gc,
+                                 int NR, T *omp, T *omdp, hipStream_t st)
+{
+    const long long work = 2ll * ne * Gc + (long long)p * Gc;
+    hipLaunchKernelGGL(refresh_layout_kernel<T>, dim3(grid_for(work, 4096)), dim3(kThreads), 0, st,
+                       omega, edges, ne, p, Gr, Gc, NR, omp, omdp);
+    return hipGetLastError();
+}
 
 template <typename T>
 hipError_t launch_support_edges(const T *omega, int p, int *count, int *edges, long long cap,
@@ -91,7 +134,9 @@ hipError_t launch_scatter_omega(const T *omp, const T *omdp, const int *part, in
     template hipError_t launch_support_edges<T>(const T *, int, int *, int *, long long,        \
                                                 hipStream_t);                                    \
     template hipError_t launch_scatter_omega<T>(const T *, const T *, const int *, int, int, int, \
-                                                int, int, T *, hipStream_t);
+                                                int, int, T *, hipStream_t);                     \
+    template hipError_t launch_refresh_layout<T>(const T *, const int *, int, int, int, int, int, \
+                                                 T *, T *, hipStream_t);
 
 CONCORD_ACTIVE_INST(float)
 CONCORD_ACTIVE_INST(double)

@@ -244,8 +244,12 @@ int fit_impl(concord_input kind, const void *X, int64_t n64, int64_t p64, double
     const int amax = active ? (opts->active_maxit > 0 ? opts->active_maxit : 20 * maxit) : 0;
     const int Mmax = active ? std::max(C.m, 2 * p) : C.m;
     const long long ecap = active ? (long long)p * (p - 1) / 2 : 0;
-    const size_t oOmp = cv.take<T>((size_t)G * Mmax * sh.nr_max);
+    const size_t oOmp = cv.take<T>((size_t)G * C.m * sh.nr_max);
     const size_t oOmdp = cv.take<T>((size_t)G * sh.nr_max);
+    // active-set sweeps keep the colouring's layout apart from Algorithm 1's,
+    // which then needs only the support pairs and the diagonal refreshed
+    const size_t oOmpT = cv.take<T>(active ? (size_t)G * Mmax * sh.nr_max : 1);
+    const size_t oOmdpT = cv.take<T>(active ? (size_t)G * sh.nr_max : 1);
     const size_t oSd = cv.take<T>(p);
     const size_t PS = (size_t)sh.Gr * sh.nr_max;  // published slots per colour
     const size_t oPc = cv.take<T>(2 * (size_t)Mmax * PS);
@@ -329,6 +333,7 @@ int fit_impl(concord_input kind, const void *X, int64_t n64, int64_t p64, double
         CK_HIP(launch_sweep<T>(P, sh.threads, stream));
     } else {
         int *edges = (int *)(B + oEdges), *ecount = (int *)(B + oEcount), *dpart = (int *)(B + oPart);
+        T *ompT = (T *)(B + oOmpT), *omdpT = (T *)(B + oOmdpT);
         std::vector<unsigned long long> lred(4 * (size_t)redsw);
         std::vector<int> hpart;  // partner table of the current colouring (host copy)
         int lout[kOutWords];
@@ -378,23 +383,28 @@ int fit_impl(concord_input kind, const void *X, int64_t n64, int64_t p64, double
                                   hipMemcpyHostToDevice, stream));
             CK_HIP(hipStreamSynchronize(stream));
             // the sweep layout of that colouring, from the dense Omega
-            CK_HIP(launch_init_omega<T>((const T *)omega, p, sh.Gr, sh.Gc, sh.nr_max, omp, omdp,
+            CK_HIP(launch_init_omega<T>((const T *)omega, p, sh.Gr, sh.Gc, sh.nr_max, ompT, omdpT,
                                         out + 4, stream, dpart, mt));
             CK_HIP(launch_init_publish<T>(W, p, sh.Gr, sh.nr_max, pc, pd, stream, dpart, mt));
             P.part = dpart;
             P.m_tab = mt;
+            P.omp = ompT;
+            P.omdp = omdpT;
             rc = run(amax);
+            P.omp = omp;
+            P.omdp = omdp;
             if (rc)
                 return rc;
             a_sweeps += lout[0];
             if (lout[4] || lout[2] || lout[3])
                 break;
-            // back to Algorithm 1's layout
+            // back to Algorithm 1's layout: only the coloured support pairs and
+            // the diagonal moved since it was last written
             CK_HIP(launch_fill<T>((T *)omega, (long long)pp, T(0), stream));
-            CK_HIP(launch_scatter_omega<T>(omp, omdp, dpart, mt, sh.Gr, sh.Gc, sh.nr_max, p,
+            CK_HIP(launch_scatter_omega<T>(ompT, omdpT, dpart, mt, sh.Gr, sh.Gc, sh.nr_max, p,
                                            (T *)omega, stream));
-            CK_HIP(launch_init_omega<T>((const T *)omega, p, sh.Gr, sh.Gc, sh.nr_max, omp, omdp,
-                                        out + 4, stream));
+            CK_HIP(launch_refresh_layout<T>((const T *)omega, edges, ne, p, sh.Gr, sh.Gc,
+                                            sh.nr_max, omp, omdp, stream));
             CK_HIP(launch_init_publish<T>(W, p, sh.Gr, sh.nr_max, pc, pd, stream));
         }
         P.part = nullptr;

@@ -35,6 +35,12 @@ hipError_t launch_support_edges(const T *omega, int p, int *count, int *edges, l
 template <typename T>
 hipError_t launch_scatter_omega(const T *omp, const T *omdp, const int *part, int mt, int Gr,
                                 int Gc, int NR, int p, T *omega, hipStream_t st);
+// Algorithm 1's layout (omp, omdp) after sweeps over a colouring of the
+// support: rewrite the ne listed pairs (edges[2 e], edges[2 e + 1]) and the
+// diagonal from the dense omega, in every column slice's copy.
+template <typename T>
+hipError_t launch_refresh_layout(const T *omega, const int *edges, int ne, int p, int Gr, int Gc,
+                                 int NR, T *omp, T *omdp, hipStream_t st);
 
 // Adjoint system of the implicit gradient (adjoint.hip).
 template <typename T>
