@@ -94,7 +94,7 @@ typedef struct {
      * colouring, Section 4): 1 = after each full sweep of Algorithm 1 that has
      * not converged, colour the support of Omega greedily and sweep over
      * those colours (then the diagonal) until their delta < tol or
-     * active_maxit sweeps (0 = 20 maxit); only full sweeps decide convergence
+     * active_maxit sweeps (0 = 3); only full sweeps decide convergence
      * and count in info->sweeps and maxit.  0 = plain Algorithm 1. */
     int32_t active_set;
     int32_t active_maxit;

@@ -241,7 +241,9 @@ int fit_impl(concord_input kind, const void *X, int64_t n64, int64_t p64, double
     // Active-set sweeps colour the support greedily: at most 2 Delta - 1 <
     // 2 p colours, so the sweep layout is sized for that many.
     const bool active = opts && opts->active_set;
-    const int amax = active ? (opts->active_maxit > 0 ? opts->active_maxit : 20 * maxit) : 0;
+    // a few active sweeps per phase: converging the coloured support far below
+    // what the next full sweep will change wastes sweeps (measured best: 3)
+    const int amax = active ? (opts->active_maxit > 0 ? opts->active_maxit : 3) : 0;
     const int Mmax = active ? std::max(C.m, 2 * p) : C.m;
     const long long ecap = active ? (long long)p * (p - 1) / 2 : 0;
     const size_t oOmp = cv.take<T>((size_t)G * C.m * sh.nr_max);

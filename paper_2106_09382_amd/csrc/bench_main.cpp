@@ -3,7 +3,7 @@
 //
 //   concord_bench --y FILE --n N --p P [--lam L] [--tol T] [--maxit K]
 //                 [--reps R] [--f32] [--row-groups A] [--col-slices B]
-//                 [--threads C] [--depth D] [--active]
+//                 [--threads C] [--depth D] [--active [--active-maxit K]]
 //   concord_bench --copy MIB
 //   concord_bench --y FILE --y2 FILE2 --lam2 L2 --n N --p P [...]
 //   concord_bench --batched DIR [--plan FILE] [--tol T] [--maxit K] [--reps R]
@@ -42,7 +42,8 @@ void usage()
     std::fprintf(stderr,
                  "usage: concord_bench --y FILE --n N --p P [--lam L] [--tol T] [--maxit K] "
                  "[--reps R] [--f32] [--row-groups A] [--col-slices B] [--threads C] "
-                 "[--depth D] [--active] [--y2 FILE2 --lam2 L2]\n       concord_bench --copy MIB\n"
+                 "[--depth D] [--active [--active-maxit K]] [--y2 FILE2 --lam2 L2]\n"
+                 "       concord_bench --copy MIB\n"
                  "       concord_bench --batched DIR [--plan FILE] [--tol T] [--maxit K] "
                  "[--reps R]\n"
                  "       concord_bench --backward --y FILE --n N --p P [--lam L] [--tol T] "
@@ -200,6 +201,8 @@ int main(int argc, char **argv)
             opt.pending_depth = std::atoi(next());
         else if (a == "--active")
             opt.active_set = 1;
+        else if (a == "--active-maxit")
+            opt.active_maxit = std::atoi(next());
         else if (a == "--backward")
             backward = 1;
         else if (a == "--batched")

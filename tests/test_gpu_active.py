@@ -92,20 +92,22 @@ def test_active_set_edge_cases(lib):
 
 
 @pytest.mark.slow
-def test_active_set_full_size(lib):
-    # p = 5000 (the benchmark's data), lambda = 0.2: the scheme's answer
-    # against the plain solve, and far fewer colour steps.
+@pytest.mark.parametrize("lam", [0.1, 0.2])
+def test_active_set_full_size(lib, lam):
+    # p = 5000 (the benchmark's data), the default cap of active sweeps per
+    # phase: the scheme's answer against the plain solve, fewer full sweeps
+    # and less device time.
     pr = datagen.problem(3)
     S = oracle.gram(pr["y"])
     tol = 1e-6
-    plain, pinfo = _fit(lib, S, 0.2, tol, 500)
-    got, info = _fit(lib, S, 0.2, tol, 500, active_set=True)
+    plain, pinfo = _fit(lib, S, lam, tol, 500)
+    got, info = _fit(lib, S, lam, tol, 500, active_set=True)
     assert info["code"] == 0 and pinfo["code"] == 0
     assert np.abs(got - plain).max() <= 1e2 * tol
     bad = (got != 0) != (plain != 0)
     np.fill_diagonal(bad, False)
     if bad.any():
-        for i, j in oracle.borderline_pairs(S, plain, 0.2, 1e-4):
+        for i, j in oracle.borderline_pairs(S, plain, lam, 1e-4):
             bad[i, j] = bad[j, i] = False
     assert not bad.any()
     assert info["sweeps"] < pinfo["sweeps"]
