@@ -210,3 +210,19 @@ def test_fullsize_fixed_point_and_shape_independence(lib, fullsize):
     h1, h2, hinfo = _gpu(lib, S1, S2, lam1, lam2, tol, 500, row_groups=32, col_slices=4)
     assert hinfo["sweeps"] == info["sweeps"]
     assert np.array_equal(h1, g1) and np.array_equal(h2, g2)
+
+
+def test_y_input_with_different_sample_sizes(lib):
+    # n_1 != n_2: each population's S is its own Y^T Y / n_m (the S-scale
+    # objective weighs the two losses equally)
+    jp1 = datagen.joint_problem(18, p=90, n=60)
+    jp2 = datagen.joint_problem(18, p=90, n=200)
+    Y1 = torch.tensor(jp1["y"][0], device="cuda")
+    Y2 = torch.tensor(jp2["y"][1], device="cuda")
+    a1, a2, ia = lib.fit_joint(Y1, Y2, 0.15, 0.03, 1e-11, 3000, kind="Y")
+    b1, b2, ib = lib.fit_joint(lib.gram(Y1), lib.gram(Y2), 0.15, 0.03, 1e-11, 3000)
+    assert torch.equal(a1, b1) and torch.equal(a2, b2) and ia["sweeps"] == ib["sweeps"]
+    S1, S2 = oracle.gram(jp1["y"][0]), oracle.gram(jp2["y"][1])
+    w1, w2, winfo, _ = joint.pcd(S1, S2, 0.15, 0.03, 1e-11, 3000)
+    assert winfo["converged"]
+    assert np.abs(a1.cpu().numpy() - w1).max() < 1e-8 and np.abs(a2.cpu().numpy() - w2).max() < 1e-8
