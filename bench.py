@@ -385,6 +385,33 @@ def cache_fp64_measurement(tol: float, shape: dict) -> dict:
             "us_per_colour_step": t * 1e3 / max(last["sweeps"] * m, 1)}
 
 
+def lds_measurement(shape: dict) -> dict:
+    """ER p = 1001 (odd: 1001 colours), n = 500, lambda = 0.2, tol 1e-7: W in
+    LDS, the sync-bound regime; FP64 and FP32."""
+    import numpy as np
+    import torch
+
+    from paper_2106_09382_amd import _lib, datagen
+
+    pr = datagen.problem(2)
+    p = pr["p"]
+    m = p + (p & 1) - 1
+    out = {"workload": f"ER p={p}, n={pr['n']}, lambda={pr['lam']}, tol={pr['tol']}, from Y"}
+    for dt, name in ((torch.float64, "f64"), (torch.float32, "f32")):
+        Y = torch.tensor(pr["y"], dtype=dt, device="cuda")
+        infos = []
+        for _ in range(4):
+            _, info = _lib.fit(Y, pr["lam"], pr["tol"], pr["maxit"], kind="Y", check=False, **shape)
+            torch.cuda.synchronize()
+            infos.append(info)
+        t = float(np.mean([i["sweep_ms"] for i in infos[1:]]))
+        last = infos[-1]
+        out[name] = {"sweep_kernel_ms": t, "sweeps": last["sweeps"], "code": last["code"],
+                     "w_in_lds": last["w_in_lds"], "workgroups": last["row_groups"] * last["col_slices"],
+                     "us_per_colour_step": t * 1e3 / max(last["sweeps"] * m, 1)}
+    return out
+
+
 def joint_measurement() -> dict:
     """Joint estimation of two populations (p = 5000, n = 2000 each, ER graphs
     differing in 10 % of their edges) against estimating them separately."""
@@ -697,6 +724,7 @@ def main() -> int:
                                          float(np.mean(sweep_ms)) / max(sweeps, 1), m)
         res["fp32"] = fp32_measurement(Y, args.lam, args.tol, shape)
         res["cache_fp64"] = cache_fp64_measurement(args.tol, shape)
+        res["lds_p1001"] = lds_measurement(shape)
         res["active_set"] = active_measurement(Y, args.tol, shape)
         if args.graph == "er":
             res["chain"] = chain_measurement(args.p, args.n, args.tol, shape)
