@@ -128,10 +128,16 @@ double oracle_diag_update(const double *S, const double *om, int p, int i)
 }
 
 /*
- * Round-robin table of Section 3.2 / Algorithm 1, written out literally.
- * The index vector (j_1..j_pe) starts as (1..pe); step k's target set pairs
- * position q with position pe - q + 1; after each step, j_pe moves to
- * position 2 and positions 2..pe-1 shift right by one (position 1 is fixed).
+ * Round-robin table of Section 3.2 / Algorithm 1, from the geometry of the
+ * circle method.  The first index (vertex 0 here) stays at the centre; the
+ * other m = pe - 1 vertices sit on a circle of m seats, vertex v on seat
+ * v - 1 at the start.  The table pairs the centre with the vertex on the
+ * seat that faces it (the axis), and every other vertex with its mirror
+ * image across the axis.  Each step turns the circle by one seat, so the
+ * axis moves one seat back: at step k it is seat c = m - 1 - k (mod m).
+ * Slot 0 is (centre, axis vertex); slot q >= 1 is the mirror pair q seats
+ * either side of the axis, the seat c + q first (the order in which the
+ * target set of step (ii) lists its pairs).
  *
  * Output: pairs[(k * H + q) * 2 + {0,1}] for step k in [0, pe-1), slot q in
  * [0, pe/2), as 0-based vertex numbers.  For odd p the value p is the
@@ -143,21 +149,21 @@ int oracle_round_robin(int p, int32_t *pairs)
     if (p < 1)
         return -1;
     int pe = p + (p & 1), H = pe / 2, m = pe - 1;
-    int *jv = (int *)malloc(sizeof(int) * pe);
-    for (int s = 0; s < pe; ++s)
-        jv[s] = s + 1;
+    /* seat[s] = vertex on seat s before any turn */
+    int *seat = (int *)malloc(sizeof(int) * (m > 0 ? m : 1));
+    for (int s = 0; s < m; ++s)
+        seat[s] = s + 1;
     for (int k = 0; k < m; ++k) {
-        for (int q = 0; q < H; ++q) {
-            pairs[((size_t)k * H + q) * 2 + 0] = jv[q] - 1;
-            pairs[((size_t)k * H + q) * 2 + 1] = jv[pe - 1 - q] - 1;
+        int axis = ((m - 1 - k) % m + m) % m;
+        int32_t *out = pairs + (size_t)k * H * 2;
+        out[0] = 0;
+        out[1] = seat[axis];
+        for (int q = 1; q < H; ++q) {
+            out[2 * q + 0] = seat[(axis + q) % m];
+            out[2 * q + 1] = seat[(axis - q + m) % m];
         }
-        int tmp = jv[pe - 1];
-        for (int s = pe - 1; s >= 2; --s)
-            jv[s] = jv[s - 1];
-        if (pe >= 2)
-            jv[1] = tmp;
     }
-    free(jv);
+    free(seat);
     return m;
 }
 

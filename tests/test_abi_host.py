@@ -2,7 +2,8 @@
 
 * The library loads and exports every function include/concord.h declares.
 * concord_schedule (the closed form the kernels use) equals the oracle's
-  literal round-robin rotation bit for bit, slot order included.
+  round-robin table (the circle method of Section 3.2, built seat by seat)
+  bit for bit, slot order included.
 * Invalid arguments are rejected before any device work.
 """
 import ctypes
@@ -43,7 +44,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 @pytest.mark.parametrize("p", list(range(1, 130)) + [255, 256, 1000, 1001, 2000, 2001])
-def test_closed_form_schedule_matches_literal_rotation(p):
+def test_closed_form_schedule_matches_oracle_table(p):
     from paper_2106_09382_amd import _lib
     assert np.array_equal(_lib.schedule(p), oracle.round_robin(p))
 

@@ -1,7 +1,11 @@
-"""Pins for the oracle's literal round-robin table (Section 3.2, Algorithm 1).
+"""Pins for the oracle's round-robin table (Section 3.2, Algorithm 1).
 
 * Table 1 (Section 2.2) lists the K_6 colouring colour by colour; the
-  literal rotation must reproduce it in order.
+  oracle's table must reproduce it in order.
+* Section 3.2's steps (ii) and (iv): each step's target set pairs the q-th
+  index with the (p_even - q + 1)-th, and between steps the index vector turns
+  by one place with its first entry fixed.  Rebuilding the index vector from
+  each step of the table and checking that turn pins the slot order.
 * Theorem 1 (Baranyai special case) and Section 3.2: p - 1 colours for even p,
   p for odd p; p/2 (even) or (p - 1)/2 (odd) real pairs per colour.
 * An edge colouring: every edge of K_p appears exactly once per sweep, and
@@ -83,3 +87,27 @@ def test_first_table_is_identity_pairing():
         tab = oracle.round_robin(p)
         want = [(q, pe - 1 - q) for q in range(pe // 2)]
         assert [tuple(map(int, x)) for x in tab[0]] == want
+
+
+def _index_vector(tab_k, pe):
+    # Step (ii): slot q (0-based) holds positions q and pe - 1 - q.
+    v = np.empty(pe, dtype=np.int64)
+    for q, (a, b) in enumerate(tab_k):
+        v[q], v[pe - 1 - q] = a, b
+    return v
+
+
+@pytest.mark.parametrize("p", [2, 3, 4, 6, 7, 10, 33, 64, 101, 256])
+def test_index_vector_turns_one_place_per_step(p):
+    # Step (iv): after each step the last index moves to position 2 and
+    # positions 2..pe-1 move one place right; position 1 never moves.  The
+    # first vector is the identity (1..pe).
+    pe = p + (p & 1)
+    tab = oracle.round_robin(p)
+    prev = _index_vector(tab[0], pe)
+    assert np.array_equal(prev, np.arange(pe))
+    for k in range(1, tab.shape[0]):
+        cur = _index_vector(tab[k], pe)
+        assert cur[0] == 0
+        assert np.array_equal(cur[1:], np.roll(prev[1:], 1))
+        prev = cur
