@@ -27,15 +27,20 @@ constexpr long long kSpinLimit = 1ll << 22;  // polls (~1 us each) before a barr
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
-// Carves one stream-ordered allocation into the solve's buffers.
+// Carves one stream-ordered allocation into the solve's buffers.  The free is
+// stream-ordered too, and the call waits for it: when the entry point returns
+// nothing of its own is still queued on the caller's stream (a free still in
+// flight at process exit would leave the runtime's teardown to retire it).
 struct Workspace {
     void *base = nullptr;
     size_t bytes = 0;
     hipStream_t stream = nullptr;
     ~Workspace()
     {
-        if (base)
+        if (base) {
             (void)hipFreeAsync(base, stream);
+            (void)hipStreamSynchronize(stream);
+        }
     }
 };
 

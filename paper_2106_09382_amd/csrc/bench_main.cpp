@@ -156,7 +156,7 @@ int run_batched(const std::string &dir, const std::string &plan, double tol, int
 
 }  // namespace
 
-int main(int argc, char **argv)
+int run(int argc, char **argv)
 {
     std::string path, path2, bdir, plan;
     double lam2 = 0.0;
@@ -371,4 +371,20 @@ int main(int argc, char **argv)
     (void)hipFree(dY);
     (void)hipFree(dOm);
     return rc < 0 ? 1 : 0;
+}
+
+// Before the process ends: wait for every queued operation on the device,
+// return the stream-ordered pool's memory, so that nothing the driver or the
+// library issued is left for the runtime's exit-time teardown to retire.
+int main(int argc, char **argv)
+{
+    const int rc = run(argc, argv);
+    (void)hipDeviceSynchronize();
+    int dev = 0;
+    hipMemPool_t pool = nullptr;
+    if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess &&
+        pool)
+        (void)hipMemPoolTrimTo(pool, 0);
+    (void)hipDeviceSynchronize();
+    return rc;
 }
