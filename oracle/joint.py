@@ -122,6 +122,58 @@ def kkt(S1, S2, O1, O2, lam1: float, lam2: float) -> dict:
     return dict(pairs=worst_pair, diag=worst_diag)
 
 
+def borderline_pairs(S1, S2, O1, O2, lam1: float, lam2: float, rel: float) -> np.ndarray:
+    """Pairs i < j whose block update at (Omega_1, Omega_2) takes a decision
+    that rounding may flip (the joint analogue of the single solve's
+    borderline filter, for reading R22's case order).
+
+    From the eq. (3) numerators b_m and a_m = S^m_ii + S^m_jj of each pair,
+    the block minimiser decides, in order: case x_1 > x_2 (the two thresholds
+    |b_1 + lam2| and |b_2 - lam2| against lam1, then u_1 > u_2); if not, case
+    x_1 < x_2 (|b_1 - lam2|, |b_2 + lam2| against lam1, then v_1 < v_2); if
+    not, the fused value (|b_1 + b_2| against 2 lam1).  A pair is borderline
+    when a decision it reaches is within rel (a_1 + a_2) of its threshold, or
+    a comparison of candidate values within rel (two candidates that are both
+    exactly 0 tie under any rounding and do not count).  Returns a (k, 2)
+    index array.
+    """
+    S1, S2, O1, O2 = _f64(S1), _f64(S2), _f64(O1), _f64(O2)
+    p = S1.shape[0]
+    iu = np.triu_indices(p, 1)
+    a, b = [], []
+    for S, O in ((S1, O1), (S2, O2)):
+        so = S @ O
+        d = np.diag(S)
+        am = (d[:, None] + d[None, :])[iu]
+        a.append(am)
+        b.append((so + so.T)[iu] - am * O[iu])
+    a1, a2, b1, b2 = a[0], a[1], b[0], b[1]
+    width = rel * (a1 + a2)
+
+    def soft(x, t):
+        return np.sign(x) * np.maximum(np.abs(x) - t, 0.0)
+
+    def near(x, t):  # a threshold decision |x| vs t within the band
+        return np.abs(np.abs(x) - t) < width
+
+    ta1, ta2 = -(b1 + lam2), -(b2 - lam2)
+    u1, u2 = soft(ta1, lam1) / a1, soft(ta2, lam1) / a2
+    case_a = u1 > u2
+    # two candidates that are both exactly 0 (both thresholds clear of their
+    # bands) compare equal under any rounding: not a borderline tie
+    def tie(x, y):
+        return (np.abs(x - y) < rel) & ((x != 0.0) | (y != 0.0))
+
+    flag = near(ta1, lam1) | near(ta2, lam1) | tie(u1, u2)
+    tb1, tb2 = -(b1 - lam2), -(b2 + lam2)
+    v1, v2 = soft(tb1, lam1) / a1, soft(tb2, lam1) / a2
+    case_b = ~case_a & (v1 < v2)
+    flag |= ~case_a & (near(tb1, lam1) | near(tb2, lam1) | tie(v1, v2))
+    fused = ~case_a & ~case_b
+    flag |= fused & near(-(b1 + b2), 2.0 * lam1)
+    return np.stack([iu[0][flag], iu[1][flag]], axis=1)
+
+
 def block_update_at(S1, S2, O1, O2, i: int, j: int, lam1: float, lam2: float):
     """The new (omega^1_ij, omega^2_ij) (i != j) or (omega^1_ii, omega^2_ii)
     (i == j) that one block update would give at (Omega_1, Omega_2): the eq.

@@ -2,8 +2,9 @@
 against the oracle (oracle/joint.py), through the C ABI.
 
 * FP64: every element within 1e-8 of the oracle's joint PCD on the same S
-  bytes, the same supports (up to borderline pairs) and the same number of
-  pairs that differ between the populations, the same sweep count; one
+  bytes; pair by pair the same support in each population and the same
+  fused pattern (which pairs differ between the populations), leaving out
+  only blocks whose case decision is within rounding; the same sweep count; one
   workgroup per population and several, odd and even p, W in LDS and in
   HBM, ragged row groups and column slices.
 * lam2 = 0 and a fixed sweep count: bit for bit two independent GPU solves.
@@ -57,13 +58,24 @@ def _gpu(lib, S1, S2, lam1, lam2, tol, maxit, dtype=torch.float64, **kw):
     return o1.double().cpu().numpy(), o2.double().cpu().numpy(), info
 
 
-def _support_equal(S, got, want, lam, rel):
-    bad = (got != 0) != (want != 0)
-    np.fill_diagonal(bad, False)
-    if bad.any():
-        for i, j in oracle.borderline_pairs(S, want, lam, rel):
-            bad[i, j] = bad[j, i] = False
-    return not bad.any()
+def _patterns_equal(S1, S2, g1, g2, w1, w2, lam1, lam2, rel):
+    """Pair by pair (i < j): the support of each population and the fused
+    pattern (omega^1_ij != omega^2_ij) agree, leaving out only the blocks
+    whose case decision at the oracle's estimate is within rounding
+    (oracle.joint.borderline_pairs, reading R22).  Returns the mismatches."""
+    p = S1.shape[0]
+    iu = np.triu_indices(p, 1)
+    keep = np.ones(iu[0].size, dtype=bool)
+    bl = joint.borderline_pairs(S1, S2, w1, w2, lam1, lam2, rel)
+    if len(bl):
+        lin = {int(i) * p + int(j) for i, j in bl}
+        keep = np.array([int(i) * p + int(j) not in lin for i, j in zip(*iu)])
+    out = {}
+    for name, a, b in (("support 1", g1[iu] != 0, w1[iu] != 0),
+                       ("support 2", g2[iu] != 0, w2[iu] != 0),
+                       ("fused pattern", g1[iu] != g2[iu], w1[iu] != w2[iu])):
+        out[name] = int(((a != b) & keep).sum())
+    return out
 
 
 CASES = [
@@ -96,11 +108,11 @@ def test_joint_fp64_matches_oracle(lib, p, n, lam1, lam2, seed, opts):
     assert info["sweeps"] == winfo["sweeps"]
     assert np.abs(g1 - w1).max() <= 1e-8 and np.abs(g2 - w2).max() <= 1e-8
     assert np.array_equal(g1, g1.T) and np.array_equal(g2, g2.T)
-    assert _support_equal(S1, g1, w1, lam1, 1e-9) and _support_equal(S2, g2, w2, lam1, 1e-9)
+    mism = _patterns_equal(S1, S2, g1, g2, w1, w2, lam1, lam2, 1e-9)
+    assert all(v == 0 for v in mism.values()), mism
     assert info["nnz_upper"] == tuple(int((np.triu(g, 1) != 0).sum()) for g in (g1, g2))
     iu = np.triu_indices(p, 1)
     assert info["differ_upper"] == int((g1[iu] != g2[iu]).sum())
-    assert abs(info["differ_upper"] - winfo["differ_upper"]) <= max(2, p // 50)
     if opts.get("row_groups"):
         assert info["row_groups"] == min(opts["row_groups"], p)
 
@@ -133,6 +145,8 @@ def test_fp32_close_to_fp64_oracle(lib):
     assert info["code"] in (0, 1)
     w1, w2, _, _ = joint.pcd(S1, S2, 0.2, 0.05, max(info["tol_eff"], 1e-12), 3000)
     assert np.abs(g1 - w1).max() <= 1e-4 and np.abs(g2 - w2).max() <= 1e-4
+    mism = _patterns_equal(S1, S2, g1, g2, w1, w2, 0.2, 0.05, 1e-4)
+    assert all(v == 0 for v in mism.values()), mism
 
 
 def test_y_input_equals_s_input(lib):

@@ -306,3 +306,78 @@ def test_joint_matches_a_general_convex_solver(p, seed, lam1, lam2, min_fused):
     # entries on the fused line omega^1_ij = omega^2_ij (i <= j)
     iu = np.triu_indices(p)
     assert int((O1[iu] == O2[iu]).sum()) >= min_fused
+
+
+# ---------------------------------------------------------------- borderline filter
+
+def _two_by_two(r1, r2):
+    """p = 2, unit diagonals, off-diagonals r_1, r_2, at Omega = I: a_m = 2 and
+    the eq. (3) numerator b_m = 2 r_m (nothing else enters)."""
+    S1 = np.array([[1.0, r1], [r1, 1.0]])
+    S2 = np.array([[1.0, r2], [r2, 1.0]])
+    return S1, S2, np.eye(2), np.eye(2)
+
+
+@pytest.mark.parametrize("r1,r2,border,why", [
+    # b = (-0.6, -0.5): |b_1 + lam2| = |b_2 - lam2| = 0.55, so u_1 = u_2 exactly
+    (-0.3, -0.25, True, "u_1 = u_2: the x_1 > x_2 test is a tie"),
+    # b_1 = -0.15: |b_1 + lam2| = lam1 in the case x_1 > x_2 that is taken
+    (-0.075, 0.2, True, "threshold of x_1 in case x_1 > x_2"),
+    # b_1 = b_2 = -0.1: fused, |b_1 + b_2| = 2 lam1
+    (-0.05, -0.05, True, "fused threshold"),
+    # b = (-0.6, 0.4): case x_1 > x_2 by 0.35, thresholds far
+    (-0.3, 0.2, False, "clear case x_1 > x_2"),
+    # b = (0.4, -0.6): case x_1 < x_2
+    (0.2, -0.3, False, "clear case x_1 < x_2"),
+    # b_1 = b_2 = -0.6: fused, far from every threshold
+    (-0.3, -0.3, False, "clear fused pair"),
+    # b = 0: every candidate is exactly 0, a tie no rounding can break
+    (0.0, 0.0, False, "zero block"),
+])
+def test_joint_borderline_pairs_on_constructed_blocks(r1, r2, border, why):
+    """Constructed blocks whose decisions sit exactly on (or clearly off) the
+    case boundaries of the block minimiser, at lam1 = 0.1, lam2 = 0.05.  A
+    missing or mis-signed lam2 shift, or the fused threshold taken at lam1
+    instead of 2 lam1, moves one of the first three off its boundary."""
+    S1, S2, O1, O2 = _two_by_two(r1, r2)
+    got = joint.borderline_pairs(S1, S2, O1, O2, 0.1, 0.05, 1e-9)
+    assert (len(got) == 1) == border, why
+    if border:
+        assert tuple(got[0]) == (0, 1)
+
+
+def test_joint_borderline_pairs_agree_with_the_block_update():
+    """Nudging the numerators of a flagged block by a few rounding units flips
+    one of the block minimiser's decisions (fused or not, zero or not); for an
+    unflagged block no such nudge changes any decision."""
+    lam1, lam2 = 0.1, 0.05
+    eps = (-1e-12, 0.0, 1e-12)
+
+    def outcomes(r1, r2):
+        b1, b2 = 2 * r1, 2 * r2
+        seen = set()
+        for e1 in eps:
+            for e2 in eps:
+                x1, x2 = joint.pair(2.0, b1 + e1, 2.0, b2 + e2, lam1, lam2)
+                seen.add((x1 != x2, x1 != 0.0, x2 != 0.0))
+        return seen
+
+    for r1, r2 in ((-0.3, -0.25), (-0.075, 0.2), (-0.05, -0.05)):
+        assert len(outcomes(r1, r2)) > 1, (r1, r2)
+    for r1, r2 in ((-0.3, 0.2), (0.2, -0.3), (-0.3, -0.3), (0.0, 0.0)):
+        assert len(outcomes(r1, r2)) == 1, (r1, r2)
+
+
+@pytest.mark.parametrize("p,n,lam1,lam2,seed", [
+    (17, 40, 0.1, 0.02, 3), (64, 120, 0.1, 0.01, 5), (130, 90, 0.15, 0.03, 7),
+    (301, 150, 0.2, 0.1, 9),
+])
+def test_no_borderline_pairs_on_the_parity_workloads(p, n, lam1, lam2, seed):
+    """Reading R22's claim for the GPU parity workloads: at the converged
+    joint estimate no block decision is within rounding of its boundary, so
+    the pair-by-pair comparisons exclude nothing."""
+    jp = datagen.joint_problem(seed, p=p, n=n, changed=0.2)
+    S1, S2 = oracle.gram(jp["y"][0]), oracle.gram(jp["y"][1])
+    O1, O2, info, _ = joint.pcd(S1, S2, lam1, lam2, 1e-10, 3000)
+    assert info["converged"]
+    assert len(joint.borderline_pairs(S1, S2, O1, O2, lam1, lam2, 1e-9)) == 0
