@@ -86,6 +86,24 @@ def test_invalid_arguments_return_einval(lib, kw):
     assert rc == -1 and info.status == -1
 
 
+@pytest.mark.parametrize("rows,cols,threads", [(32, 8, 512), (16, 16, 256), (1, 1, 64)])
+def test_rows_per_thread_cap_returns_elaunch(lib, rows, cols, threads):
+    """A workgroup holds at most two rows of W per thread, so a launch of
+    `rows` row groups of `threads` threads serves p <= 2 * threads * rows; one
+    more row is refused with CONCORD_ELAUNCH while the launch shape is chosen,
+    before any device work (the input pointers here are not device memory)."""
+    from paper_2106_09382_amd import _lib
+    cap = 2 * threads * rows
+    opts = _lib.ConcordOptions()
+    opts.row_groups, opts.col_slices, opts.block_threads = rows, cols, threads
+    info = _lib.ConcordInfo()
+    for dt in (0, 1):
+        rc = lib.concord_fit_ex(0, ctypes.c_void_p(0x1000), 0, cap + 1, 0.1, 1e-6, 10, dt, None,
+                                ctypes.c_void_p(0x2000), ctypes.byref(info), None,
+                                ctypes.byref(opts))
+        assert rc == _lib.ELAUNCH
+
+
 def test_gram_rejects_bad_sizes(lib):
     assert lib.concord_gram(None, 10, 10, 1, ctypes.c_void_p(0x10), None) == -1
     assert lib.concord_gram(ctypes.c_void_p(0x10), 0, 10, 1, ctypes.c_void_p(0x10), None) == -1

@@ -3,6 +3,13 @@ in the launch configuration bench.py times (the default shape).
 
 * One sweep from the identity against the oracle's sweep (direct sums,
   about a minute of CPU): every element.
+* The converged solve (lambda = 0.1 and 0.2, tol 1e-6) against the oracle's
+  converged solve, stored by tests/golden/make_fullsize.py (an hour of CPU
+  per lambda, so it is not rerun here): FP64 every element within 1e-8, the
+  same support outside the stored borderline pairs, the same sweep count and
+  delta trace; FP32 within 1e-4 of the oracle's iterate at the sweep where
+  the FP32 stopping rule (reading R8) stops it, same support outside its
+  borderline pairs.
 * The converged solve (lambda = 0.1 and 0.2, tol 1e-6): properties that hold
   at any size, checked on outputs the oracle computes one by one -- sampled
   entries are fixed points of eqs. (2)-(3) (the oracle's coordinate updates
@@ -10,6 +17,9 @@ in the launch configuration bench.py times (the default shape).
   the reported objective is eq. (1) of the returned Omega, the result does
   not depend on the launch shape, and FP32 stays within 1e-4 of FP64.
 """
+import hashlib
+import importlib.util
+import os
 import warnings
 
 import numpy as np
@@ -18,6 +28,25 @@ import torch
 
 import oracle
 from paper_2106_09382_amd import datagen
+
+_GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _stored(lam):
+    spec = importlib.util.spec_from_file_location("make_fullsize",
+                                                  os.path.join(_GOLDEN, "make_fullsize.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod.load(lam)
+
+
+def _dense(p, lin, val, diag):
+    om = np.zeros((p, p))
+    i, j = np.divmod(lin, p)
+    om[i, j] = val
+    om[j, i] = val
+    om[np.arange(p), np.arange(p)] = diag
+    return om
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
@@ -102,3 +131,42 @@ def test_converged_solution_properties(lib, workload, lam):
         for i, j in oracle.borderline_pairs(S, om, lam, 1e-4):
             bad[i, j] = bad[j, i] = False
     assert not bad.any()
+
+
+@pytest.mark.parametrize("lam", [0.1, 0.2])
+def test_converged_solve_matches_stored_oracle(lib, workload, lam):
+    S = workload["S"]
+    p = S.shape[0]
+    ref = _stored(lam)
+    sha = hashlib.sha256(np.ascontiguousarray(S).tobytes()).hexdigest()
+    print(f"full size lam={lam}: S sha256 {'matches' if sha == str(ref['s_sha256']) else 'differs from'}"
+          " the stored one", flush=True)
+    assert int(ref["p"]) == p and bool(ref["converged"])
+    want = _dense(p, ref["upper_lin"], ref["upper_val"], ref["diag"])
+    got, info = _fit(lib, S, lam, float(ref["tol"]), int(ref["maxit"]), trace=True)
+    assert info["code"] == 0
+    err = np.abs(got - want).max()
+    assert err <= 1e-8, err
+    bad = np.triu((got != 0) != (want != 0), 1)
+    for i, j in ref["borderline"]:
+        bad[i, j] = False
+    assert not bad.any(), int(bad.sum())
+    assert info["sweeps"] == int(ref["sweeps"])
+    assert np.allclose(info["delta_trace"], ref["delta_trace"], rtol=1e-6, atol=1e-10)
+    assert info["nnz_upper"] == int(np.triu(got != 0, 1).sum())
+    if len(ref["borderline"]) == 0:
+        assert info["nnz_upper"] == ref["upper_lin"].size
+    # FP32 against the oracle's iterate at the FP32 stopping sweep
+    got32, info32 = _fit(lib, S, lam, float(ref["tol"]), int(ref["maxit"]), dtype=torch.float32)
+    assert info32["code"] in (0, 1)
+    want32 = _dense(p, ref["f32_upper_lin"], ref["f32_upper_val"].astype(np.float64),
+                    ref["f32_diag"])
+    err32 = np.abs(got32 - want32).max()
+    print(f"full size lam={lam}: FP32 {info32['sweeps']} sweeps (oracle rule: "
+          f"{int(ref['f32_sweeps'])}), tol_eff {info32['tol_eff']:.3e}, max error {err32:.2e}",
+          flush=True)
+    assert err32 <= 1e-4, err32
+    bad = np.triu((got32 != 0) != (want32 != 0), 1)
+    for i, j in ref["f32_borderline"]:
+        bad[i, j] = False
+    assert not bad.any(), int(bad.sum())
