@@ -166,21 +166,30 @@ def batched_measurement(plain_all: bool) -> dict:
 
     from paper_2106_09382_amd import autotune
 
-    def run_batch(pw=None):
+    last = {}
+
+    def run_batch(pw=None, pc=None, cpl=0):
         with warnings.catch_warnings():
             warnings.simplefilter("ignore")
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            res = _lib.fit_batched(Xs, lams, tol, maxit, kind="Y", check=False,
-                                   problem_workgroups=pw)
+            outs, infos, code = _lib.fit_batched(Xs, lams, tol, maxit, kind="Y", check=False,
+                                                 problem_workgroups=pw, problem_col_slices=pc,
+                                                 cols_per_lane=cpl)
             torch.cuda.synchronize()
-            return res, time.perf_counter() - t0
+            wall = time.perf_counter() - t0
+        if code < 0:
+            raise RuntimeError(f"batched solve failed with status {code}")
+        last[(None if pw is None else tuple(pw), None if pc is None else tuple(pc), cpl)] = \
+            (infos, code)
+        return infos, wall
 
-    (outs, infos0, code0), wall_default = run_batch()
-    log(f"bench: batched with the built-in plan: {wall_default:.2f} s")
-    total = int(sum(row[0]["row_groups"] for row in infos0))
-    tuned = autotune.plan_from_infos([int(x) for x in ps], infos0, total)
-    (outs, infos, code), wall = run_batch(tuned)
+    total = torch.cuda.get_device_properties(0).multi_processor_count
+    best = autotune.search(run_batch, [int(x) for x in ps], total, log=log)
+    wall_default = best["trials"][0]["wall_s"]
+    tuned = best["problem_workgroups"]
+    infos, code = last[(tuple(tuned), tuple(best["problem_col_slices"]), best["cols_per_lane"])]
+    wall = best["wall_s"]
     sweeps = sum(i["sweeps"] for row in infos for i in row)
     moved = np.array([sum(i["moved_pairs"] for i in row) for row in infos], dtype=float)
     mdiag = np.array([sum(i["moved_diag"] for i in row) for row in infos], dtype=float)
@@ -218,17 +227,25 @@ def batched_measurement(plain_all: bool) -> dict:
         "solves": B * L,
         "wall_s": wall,
         "wall_s_builtin_plan": wall_default,
-        "plan": "autotuned from the built-in-plan run's per-problem device times",
+        "plan": ("autotuned: workgroups dealt by measured per-problem work, each problem's "
+                 "split into row groups x column slices and the columns per lane in row "
+                 "rewrites picked from measured runs"),
+        "tuned_plan": {"problem_workgroups": [int(x) for x in tuned],
+                       "problem_col_slices": [int(x) for x in best["problem_col_slices"]],
+                       "cols_per_lane": int(best["cols_per_lane"]), "block_threads": 512,
+                       "work_model_exponent": best["work_model_exponent"]},
+        "autotune_trials": [{"tag": t["tag"], "wall_s": t["wall_s"]} for t in best["trials"]],
         "solves_per_s": B * L / wall,
         "plain_loop_s": plain_total,
         "plain_solves_per_s": B * L / plain_total,
         "speedup_vs_plain": plain_total / wall,
         "plain_loop_how": how,
         "status": code,
+        "setup_ms": float(infos[0][0]["gram_ms"]),
+        "launch_ms": float(infos[0][0]["elapsed_ms"]),
         "sweeps_total": int(sweeps),
         "algorithmic_GBs": byt / wall / 1e9,
-        "workgroups": int(sum(row[0]["row_groups"] for row in infos)),
-        "plan_workgroups": [int(x) for x in tuned],
+        "workgroups": int(sum(row[0]["row_groups"] * row[0]["col_slices"] for row in infos)),
     }
 
 

@@ -129,15 +129,24 @@ int concord_fit_ex(concord_input kind, const void *X, int64_t n, int64_t p, doub
 
 /* Launch options of the batched solver (all 0 = defaults). */
 typedef struct {
-    int32_t workgroups;     /* workgroups of one launch, <= compute units (0 = all) */
+    int32_t workgroups;     /* workgroups of one launch (0 = one per compute unit); at most
+                               one per compute unit at 512 threads, two at 256 or fewer */
     int32_t block_threads;  /* threads per workgroup, multiple of 64, <= 512 (0 = 512) */
     int32_t pending_depth;  /* 2..8 row updates held before a row is rewritten (0 = 8) */
-    int32_t reserved;
+    int32_t cols_per_lane;  /* columns of W each lane carries in a row rewrite: 2 or 4 (0 = 4) */
     /* Optional host array of B workgroup counts, one per problem (each at
-     * least ceil(p_b / (2 * block_threads)) and at most p_b, summing to at
-     * most `workgroups`): all problems then share one launch with these
-     * counts instead of the built-in plan.  NULL = built-in plan. */
+     * least ceil(p_b / (2 * block_threads)) row groups' worth and at most
+     * p_b, summing to at most `workgroups`): all problems then share one
+     * launch with these counts instead of the built-in plan.  NULL = built-in
+     * plan. */
     const int32_t *problem_workgroups;
+    /* Optional host array of B column-slice counts (requires
+     * problem_workgroups): problem b's problem_workgroups[b] workgroups form
+     * a grid of problem_workgroups[b] / c_b row groups x c_b column slices,
+     * each workgroup holding its row group's rows of W in one slice of the
+     * columns (c_b must divide the workgroup count, be <= p_b, and leave
+     * ceil(p_b / row groups) <= 2 * block_threads).  NULL = one slice each. */
+    const int32_t *problem_col_slices;
 } concord_batch_options;
 
 /*

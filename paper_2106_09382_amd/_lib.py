@@ -97,8 +97,9 @@ class ConcordBatchOptions(ctypes.Structure):
         ("workgroups", ctypes.c_int32),
         ("block_threads", ctypes.c_int32),
         ("pending_depth", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("cols_per_lane", ctypes.c_int32),
         ("problem_workgroups", ctypes.POINTER(ctypes.c_int32)),
+        ("problem_col_slices", ctypes.POINTER(ctypes.c_int32)),
     ]
 
 
@@ -327,13 +328,17 @@ def fit_joint(X1: torch.Tensor, X2: torch.Tensor, lam1: float, lam2: float, tol:
 
 def fit_batched(Xs, lambdas, tol: float = 1e-6, maxit: int = 500, *, kind: str = "S",
                 outs=None, stream=None, workgroups: int = 0, block_threads: int = 0,
-                pending_depth: int = 0, problem_workgroups=None, check: bool = True):
+                pending_depth: int = 0, problem_workgroups=None, problem_col_slices=None,
+                cols_per_lane: int = 0, check: bool = True):
     """B independent solves along lambda paths in one persistent launch.
 
     Xs: list of B device tensors (S_b, or Y_b with kind='Y'), one dtype.
     lambdas: B x L nested sequence (or one length-L sequence for all).
     Returns (omegas, infos, code): omegas[b][l] is the p_b x p_b Omega at
     lambdas[b][l] (warm-started from omegas[b][l - 1]); infos[b][l] its dict.
+    Launch options: ``problem_workgroups`` (workgroups per problem),
+    ``problem_col_slices`` (how many column slices they form), ``cols_per_lane``
+    (2 or 4) and ``block_threads``; see concord_batch_options.
     """
     import numpy as np
     lib = load()
@@ -383,13 +388,19 @@ def fit_batched(Xs, lambdas, tol: float = 1e-6, maxit: int = 500, *, kind: str =
     la = (ctypes.c_double * (B * L))(*lam.ravel().tolist())
     oa = (vp * (B * L))(*[outs[b][l].data_ptr() for b in range(B) for l in range(L)])
     infos = (ConcordInfo * (B * L))()
-    opts = ConcordBatchOptions(workgroups, block_threads, pending_depth, 0, None)
-    pw = None
+    opts = ConcordBatchOptions(workgroups, block_threads, pending_depth, cols_per_lane, None,
+                               None)
+    pw = pc = None
     if problem_workgroups is not None:
         if len(problem_workgroups) != B:
             raise ValueError("problem_workgroups needs one count per problem")
         pw = (ctypes.c_int32 * B)(*[int(x) for x in problem_workgroups])
         opts.problem_workgroups = ctypes.cast(pw, ctypes.POINTER(ctypes.c_int32))
+    if problem_col_slices is not None:
+        if len(problem_col_slices) != B:
+            raise ValueError("problem_col_slices needs one count per problem")
+        pc = (ctypes.c_int32 * B)(*[int(x) for x in problem_col_slices])
+        opts.problem_col_slices = ctypes.cast(pc, ctypes.POINTER(ctypes.c_int32))
     with torch.cuda.device(Xs[0].device):
         code = lib.concord_fit_batched_ex(B, INPUT_S if kind == "S" else INPUT_Y, xa, na, pa, L,
                                           la, float(tol), int(maxit), dt, oa, infos,

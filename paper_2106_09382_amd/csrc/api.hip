@@ -751,7 +751,8 @@ template <typename T>
 int batched_chunk(int B0, int B1, concord_input kind, const void *const *X, const int64_t *n,
                   const int64_t *pv, int L, const double *lambdas, double tol, int maxit,
                   void *const *omega, concord_info *info, hipStream_t stream,
-                  const std::vector<int> &Gb, int threads, int depth)
+                  const std::vector<int> &Gb, const std::vector<int> &Cb, int threads, int depth,
+                  int cpl)
 {
     const int NB = B1 - B0;
     hipEvent_t ev[4] = {};
@@ -768,8 +769,9 @@ int batched_chunk(int B0, int B1, concord_input kind, const void *const *X, cons
         CK_HIP(hipEventCreate(&ev[k]));
 
     // Per-problem shapes and workspace offsets.
+    // Problem q: G = Gr x Gc workgroups (row groups x column slices).
     struct Prob {
-        int p, G, nr, m;
+        int p, G, Gr, Gc, nr, nc, m;
         size_t oS, oW, oOmp, oOmdp, oSd, oPc, oPd, oFlags, oRed, oOut, oRec, oLam, oOm;
     };
     std::vector<Prob> pr(NB);
@@ -781,7 +783,12 @@ int batched_chunk(int B0, int B1, concord_input kind, const void *const *X, cons
         Prob &P = pr[q];
         P.p = (int)pv[b];
         P.G = Gb[b];
-        P.nr = (P.p + P.G - 1) / P.G;
+        P.Gc = Cb[b];
+        P.Gr = P.G / P.Gc;
+        P.nr = (P.p + P.Gr - 1) / P.Gr;
+        P.nc = 0;
+        for (int c = 0; c < P.Gc; ++c)
+            P.nc = std::max(P.nc, slice_lo(c + 1, P.Gc, P.p) - slice_lo(c, P.Gc, P.p));
         P.m = Circle::make(P.p).m;
         const size_t pp = (size_t)P.p * P.p;
         P.oS = (kind == CONCORD_INPUT_Y) ? cv.take<T>(pp) : 0;
@@ -789,7 +796,7 @@ int batched_chunk(int B0, int B1, concord_input kind, const void *const *X, cons
         P.oOmp = cv.take<T>((size_t)P.G * P.m * P.nr);
         P.oOmdp = cv.take<T>((size_t)P.G * P.nr);
         P.oSd = cv.take<T>(P.p);
-        const size_t PS = (size_t)P.G * P.nr;
+        const size_t PS = (size_t)P.Gr * P.nr;
         P.oPc = cv.take<T>(2 * (size_t)P.m * PS);
         P.oPd = cv.take<T>(2 * PS);
         P.oFlags = cv.take<unsigned>(P.G);
@@ -801,7 +808,7 @@ int batched_chunk(int B0, int B1, concord_input kind, const void *const *X, cons
         SweepParams<T> probe;
         memset(&probe, 0, sizeof(probe));
         probe.nr_max = P.nr;
-        probe.nc_max = P.p;
+        probe.nc_max = P.nc;
         probe.depth = depth;
         lds = std::max(lds, sweep_lds_bytes<T>(probe));
         Gtot += P.G;
@@ -845,8 +852,8 @@ int batched_chunk(int B0, int B1, concord_input kind, const void *const *X, cons
         if (kind == CONCORD_INPUT_Y)
             CK_HIP(launch_gram<T>((const T *)X[b], (int)n[b], P.p, S, stream));
         CK_HIP(launch_check_copy<T>(S, P.p, W, true, sd, out + 4, stream));
-        CK_HIP(launch_init_omega<T>(nullptr, P.p, P.G, 1, P.nr, omp, omdp, out + 4, stream));
-        CK_HIP(launch_init_publish<T>(W, P.p, P.G, P.nr, pc, pd, stream));
+        CK_HIP(launch_init_omega<T>(nullptr, P.p, P.Gr, P.Gc, P.nr, omp, omdp, out + 4, stream));
+        CK_HIP(launch_init_publish<T>(W, P.p, P.Gr, P.nr, pc, pd, stream));
         for (int l = 0; l < L; ++l) {
             hl[(size_t)q * L + l] = lambdas[(size_t)b * L + l];
             hom[(size_t)q * L + l] = (T *)omega[(size_t)b * L + l];
@@ -864,12 +871,12 @@ int batched_chunk(int B0, int B1, concord_input kind, const void *const *X, cons
         D.red = (unsigned long long *)(base + P.oRed);
         D.out = out;
         D.p = P.p;
-        D.Gr = P.G;
-        D.Gc = 1;
+        D.Gr = P.Gr;
+        D.Gc = P.Gc;
         D.maxit = maxit;
         D.w_lds = 0;
         D.nr_max = P.nr;
-        D.nc_max = P.p;
+        D.nc_max = P.nc;
         D.depth = depth;
         D.rpt = 2;
         D.lam = (T)hl[(size_t)q * L];
@@ -895,7 +902,8 @@ int batched_chunk(int B0, int B1, concord_input kind, const void *const *X, cons
                           stream));
     CK_HIP(hipEventRecord(ev[1], stream));
     CK_HIP(launch_sweep_batched<T>((const SweepParams<T> *)(base + oDesc),
-                                   (const int *)(base + oMap), Gtot, lds, threads, stream));
+                                   (const int *)(base + oMap), Gtot, lds, threads, cpl,
+                                   stream));
     CK_HIP(hipEventRecord(ev[2], stream));
 
     // Readback: status words, per-sweep reductions and per-lambda records.
@@ -981,8 +989,8 @@ int batched_chunk(int B0, int B1, concord_input kind, const void *const *X, cons
                                   : (double)ms_sweep;
                 I->moved_pairs = mv;
                 I->moved_diag = mvd;
-                I->row_groups = pr[q].G;
-                I->col_slices = 1;
+                I->row_groups = pr[q].Gr;
+                I->col_slices = pr[q].Gc;
                 I->w_in_lds = 0;
                 I->block_threads = threads;
                 I->pending_depth = depth;
@@ -1004,9 +1012,15 @@ int batched_impl(int B, concord_input kind, const void *const *X, const int64_t 
     int total = (o && o->workgroups > 0) ? o->workgroups : cus;
     int threads = (o && o->block_threads > 0) ? o->block_threads : 512;
     int depth = (o && o->pending_depth > 0) ? o->pending_depth : 8;
-    if (o && (o->workgroups < 0 || o->block_threads < 0 || o->pending_depth < 0))
+    const int cpl = (o && o->cols_per_lane > 0) ? o->cols_per_lane : 4;
+    if (o && (o->workgroups < 0 || o->block_threads < 0 || o->pending_depth < 0 ||
+              o->cols_per_lane < 0))
         return CONCORD_EINVAL;
-    if (total > cus || threads % 64 != 0 || threads > 512 || depth < 2 || depth > 8)
+    // co-residency of the persistent launch: one 512-thread workgroup per
+    // CU, or two of at most 256 threads
+    const int per_cu = (threads <= 256) ? 2 : 1;
+    if (total > per_cu * cus || threads % 64 != 0 || threads > 512 || depth < 2 || depth > 8 ||
+        (cpl != 2 && cpl != 4))
         return CONCORD_EINVAL;
     // Problems go in order into launches of at most `total` workgroups.
     std::vector<int> minG(B);
@@ -1022,6 +1036,21 @@ int batched_impl(int B, concord_input kind, const void *const *X, const int64_t 
         }
         if (sum > total)
             return CONCORD_EINVAL;
+    }
+    const int32_t *slices = o ? o->problem_col_slices : nullptr;
+    std::vector<int> Cb(B, 1);
+    if (slices) {
+        if (!fixed)
+            return CONCORD_EINVAL;
+        for (int b = 0; b < B; ++b) {
+            const int c = slices[b];
+            if (c < 1 || c > pv[b] || fixed[b] % c != 0)
+                return CONCORD_EINVAL;
+            const long long gr = fixed[b] / c;
+            if ((pv[b] + gr - 1) / gr > 2ll * threads)  // two rows per thread at most
+                return CONCORD_EINVAL;
+            Cb[b] = c;
+        }
     }
     std::vector<int> Gb(B, 1);
     int worst = CONCORD_OK;
@@ -1040,7 +1069,7 @@ int batched_impl(int B, concord_input kind, const void *const *X, const int64_t 
         for (int b = b0; b < b1; ++b)
             Gb[b] = G[b - b0];
         const int rc = batched_chunk<T>(b0, b1, kind, X, n, pv, L, lambdas, tol, maxit, omega,
-                                        info, stream, Gb, threads, depth);
+                                        info, stream, Gb, Cb, threads, depth, cpl);
         worst = merge_status(worst, rc);
         if (rc == CONCORD_ENOMEM || rc == CONCORD_EDEVICE || rc == CONCORD_ELAUNCH)
             return rc;

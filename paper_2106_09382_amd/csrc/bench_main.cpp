@@ -7,6 +7,7 @@
 //   concord_bench --copy MIB
 //   concord_bench --y FILE --y2 FILE2 --lam2 L2 --n N --p P [...]
 //   concord_bench --batched DIR [--plan FILE] [--tol T] [--maxit K] [--reps R]
+//                 [--threads C] [--cpl K]
 //   concord_bench --backward --y FILE --n N --p P [--lam L] [--tol T] [--reps R]
 //
 // --copy runs one device-to-device copy of MIB mebibytes (the runtime's copy
@@ -20,8 +21,10 @@
 // With --batched, DIR holds problems.txt ('p n' per problem), lambdas.txt
 // and y_<b>.bin (raw float64 n x p), as bench.py --dump-batched writes them;
 // each repetition is one FP32 concord_fit_batched_ex of all problems along
-// the lambda path, with the workgroup counts of --plan FILE (one per
-// problem) or the built-in plan.  With --backward, each repetition is one
+// the lambda path, with the workgroup plan of --plan FILE (one line per
+// problem: its workgroups, optionally followed by its column slices) or the
+// built-in plan; --threads and --cpl set the batch's threads per workgroup
+// and columns per lane in row rewrites.  With --backward, each repetition is one
 // FP64 solve from Y followed by concord_backward of
 // L = |Omega-hat - Omega_0|_F^2 with the chain Omega_0 (1 on the diagonal,
 // 0.4 beside it), the gradient workload of bench.py.
@@ -45,13 +48,14 @@ void usage()
                  "[--depth D] [--active [--active-maxit K]] [--y2 FILE2 --lam2 L2]\n"
                  "       concord_bench --copy MIB\n"
                  "       concord_bench --batched DIR [--plan FILE] [--tol T] [--maxit K] "
-                 "[--reps R]\n"
+                 "[--reps R] [--threads C] [--cpl K]\n"
                  "       concord_bench --backward --y FILE --n N --p P [--lam L] [--tol T] "
                  "[--reps R]\n");
 }
 
 // The batched workload from DIR, FP32, one launch per repetition.
-int run_batched(const std::string &dir, const std::string &plan, double tol, int maxit, int reps)
+int run_batched(const std::string &dir, const std::string &plan, double tol, int maxit, int reps,
+                int threads, int cpl)
 {
     std::vector<int64_t> ps, ns;
     {
@@ -78,12 +82,20 @@ int run_batched(const std::string &dir, const std::string &plan, double tol, int
         std::fprintf(stderr, "concord_bench: no problems or lambdas in %s\n", dir.c_str());
         return 1;
     }
-    std::vector<int32_t> pw;
+    std::vector<int32_t> pw, pc;
+    bool any_slices = false;
     if (!plan.empty()) {
         FILE *f = std::fopen(plan.c_str(), "r");
-        int x = 0;
-        while (f && std::fscanf(f, "%d", &x) == 1)
-            pw.push_back(x);
+        char line[256];
+        while (f && std::fgets(line, sizeof(line), f)) {
+            int g = 0, c = 1;
+            const int got = std::sscanf(line, "%d %d", &g, &c);
+            if (got < 1)
+                continue;
+            pw.push_back(g);
+            pc.push_back(got >= 2 ? c : 1);
+            any_slices = any_slices || got >= 2;
+        }
         if (f)
             std::fclose(f);
         if ((int)pw.size() != B) {
@@ -122,6 +134,9 @@ int run_batched(const std::string &dir, const std::string &plan, double tol, int
     concord_batch_options bo;
     std::memset(&bo, 0, sizeof(bo));
     bo.problem_workgroups = pw.empty() ? nullptr : pw.data();
+    bo.problem_col_slices = any_slices ? pc.data() : nullptr;
+    bo.block_threads = threads;
+    bo.cols_per_lane = cpl;
     std::vector<concord_info> info((size_t)B * L);
     int rc = 0;
     for (int r = 0; r < reps; ++r) {
@@ -163,7 +178,7 @@ int run(int argc, char **argv)
     int backward = 0;
     long long n = 0, p = 0, copy_mib = 0;
     double lam = 0.1, tol = 1e-6;
-    int maxit = 500, reps = 1, f32 = 0;
+    int maxit = 500, reps = 1, f32 = 0, cpl = 0;
     concord_options opt;
     std::memset(&opt, 0, sizeof(opt));
     for (int k = 1; k < argc; ++k) {
@@ -209,6 +224,8 @@ int run(int argc, char **argv)
             bdir = next();
         else if (a == "--plan")
             plan = next();
+        else if (a == "--cpl")
+            cpl = std::atoi(next());
         else if (a == "--y2")
             path2 = next();
         else if (a == "--lam2")
@@ -236,7 +253,7 @@ int run(int argc, char **argv)
         return 0;
     }
     if (!bdir.empty())
-        return run_batched(bdir, plan, tol, maxit, reps);
+        return run_batched(bdir, plan, tol, maxit, reps, opt.block_threads, cpl);
     if (path.empty() || n < 1 || p < 1 || reps < 1) {
         usage();
         return 2;

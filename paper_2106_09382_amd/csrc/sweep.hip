@@ -29,15 +29,17 @@ __global__ void __launch_bounds__(512) pcd_sweep_kernel(SweepParams<T> P)
 // single-problem kernel; the problems of a batch are small enough for their
 // W rows to stay in L2 and the last-level cache anyway).  A batch gives each
 // problem few workgroups, so row rewrites are a large part of each colour
-// step: they keep four columns per lane in flight instead of two.
-template <typename T>
+// step: by default they keep four columns per lane in flight (CPL) instead
+// of two.  A problem's workgroups may also split its columns into slices
+// (Gr x Gc per problem, from its descriptor).
+template <typename T, int CPL>
 __global__ void __launch_bounds__(512)
     pcd_batched_kernel(const SweepParams<T> *__restrict__ descs, const int *__restrict__ wg_problem)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const SweepParams<T> P = descs[wg_problem[blockIdx.x]];
     const int g = (int)blockIdx.x - P.g0, G = P.Gr * P.Gc;
-    pcd_solve<T, false, 2, 4, false, false, false>(P, g, G, smem_raw);
+    pcd_solve<T, false, 2, CPL, false, false, false>(P, g, G, smem_raw);
 }
 
 namespace {
@@ -83,9 +85,12 @@ hipError_t launch_sweep(const SweepParams<T> &P, int threads, hipStream_t stream
 
 template <typename T>
 hipError_t launch_sweep_batched(const SweepParams<T> *descs, const int *wg_problem, int G,
-                                size_t lds, int threads, hipStream_t stream)
+                                size_t lds, int threads, int cpl, hipStream_t stream)
 {
-    const void *fn = (const void *)pcd_batched_kernel<T>;
+    if (cpl != 2 && cpl != 4)
+        return hipErrorInvalidValue;
+    const void *fn = (cpl == 2) ? (const void *)pcd_batched_kernel<T, 2>
+                                : (const void *)pcd_batched_kernel<T, 4>;
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess)
         return e;
@@ -96,9 +101,9 @@ hipError_t launch_sweep_batched(const SweepParams<T> *descs, const int *wg_probl
 }
 
 template hipError_t launch_sweep_batched<float>(const SweepParams<float> *, const int *, int,
-                                                size_t, int, hipStream_t);
+                                                size_t, int, int, hipStream_t);
 template hipError_t launch_sweep_batched<double>(const SweepParams<double> *, const int *, int,
-                                                 size_t, int, hipStream_t);
+                                                 size_t, int, int, hipStream_t);
 template size_t sweep_lds_bytes<float>(const SweepParams<float> &);
 template size_t sweep_lds_bytes<double>(const SweepParams<double> &);
 template hipError_t launch_sweep<float>(const SweepParams<float> &, int, hipStream_t);

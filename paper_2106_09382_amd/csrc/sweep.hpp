@@ -127,10 +127,11 @@ hipError_t launch_sweep(const SweepParams<T> &P, int threads, hipStream_t stream
 
 // One cooperative launch over G workgroups serving several problems:
 // descs (device) holds one SweepParams per problem, wg_problem (device, G
-// entries) the problem of each workgroup; lds = the largest sweep_lds_bytes.
+// entries) the problem of each workgroup; lds = the largest sweep_lds_bytes;
+// cpl = columns per lane in row rewrites (2 or 4).
 template <typename T>
 hipError_t launch_sweep_batched(const SweepParams<T> *descs, const int *wg_problem, int G,
-                                size_t lds, int threads, hipStream_t stream);
+                                size_t lds, int threads, int cpl, hipStream_t stream);
 
 // Joint estimation: one cooperative launch of 2 G workgroups, population 0 on
 // the first G (P0) and population 1 on the rest (P1); G = Gr * Gc of both.

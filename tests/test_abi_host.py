@@ -150,10 +150,46 @@ def test_autotune_plan_deals_by_work():
     assert all(g * 8 <= p or g == autotune.min_workgroups(p) for g, p in zip(G, ps))
     heavy = autotune.plan(ps, [1.0, 10.0, 1.0, 1.0], 40)
     assert heavy[1] > G[1]
-    infos = [[{"sweep_ms": 5.0, "row_groups": g}] for g in G]
+    infos = [[{"sweep_ms": 5.0, "row_groups": g, "col_slices": 1}] for g in G]
     assert sum(autotune.plan_from_infos(ps, infos, 40)) <= 40
     with pytest.raises(ValueError):
         autotune.plan([5000] * 10, [1.0] * 10, 12)
+    # with column slices a count stays a multiple of its problem's slices
+    S = autotune.plan([3000, 2000, 400], [3.0, 2.0, 1.0], 40, slices=[2, 4, 1])
+    assert S[0] % 2 == 0 and S[1] % 4 == 0 and sum(S) <= 40
+    assert S[0] >= autotune.min_workgroups(3000, 512, 2)
+
+
+def test_autotune_search_keeps_what_measures_faster():
+    """The search on a model batch whose per-problem time is work / workgroups,
+    where two column slices halve the work of the large problems and two
+    columns per lane slow everything: it must pick the slices for exactly
+    the large problems and keep four columns per lane."""
+    from paper_2106_09382_amd import autotune
+    ps = [300, 800, 2500, 3000]
+    base = {300: 1.0, 800: 4.0, 2500: 30.0, 3000: 40.0}
+    calls = []
+
+    def run(pw, pc, cpl):
+        calls.append((pw, pc, cpl))
+        pw = pw or [8] * len(ps)
+        pc = pc or [1] * len(ps)
+        infos = []
+        for p, g, c in zip(ps, pw, pc):
+            work = base[p] * (0.5 if (c == 2 and p >= 2000) else (1.5 if c == 2 else 1.0))
+            work *= 1.2 if cpl == 2 else 1.0
+            infos.append([{"sweep_ms": work / g, "row_groups": g // c, "col_slices": c}])
+        return infos, max(r[0]["sweep_ms"] for r in infos)
+
+    best = autotune.search(run, ps, 64)
+    C = best["problem_col_slices"]
+    assert C[2] == 2 and C[3] == 2 and C[0] == 1 and C[1] == 1
+    assert best["cols_per_lane"] == 4
+    assert sum(best["problem_workgroups"]) <= 64
+    for p, g, c in zip(ps, best["problem_workgroups"], C):
+        assert g % c == 0 and -(-p // (g // c)) <= 1024
+    assert best["wall_s"] == min(t["wall_s"] for t in best["trials"])
+    assert calls[0] == (None, None, 4) and len(calls) == len(best["trials"])
 
 
 def _fit_joint(lib, opts=None, **kw):

@@ -326,3 +326,33 @@ def test_explicit_and_autotuned_plans_give_the_same_bits(lib):
     _, _, bad = _run(lib, [pr["S"] for pr in probs], LAMS, TOL, MAXIT,
                      problem_workgroups=[0] * len(ps))
     assert bad == -1
+
+
+@pytest.mark.parametrize("threads,cpl", [(512, 2), (256, 4), (256, 2)])
+def test_column_slices_and_rewrite_width_give_the_same_bits(lib, threads, cpl):
+    """Problems split into row groups x column slices, narrower workgroups
+    (two per CU) and two columns per lane in row rewrites: the same iterates,
+    bit for bit, as the default launch (and so the oracle's, checked above)."""
+    probs = _small_batch()
+    ps = [pr["p"] for pr in probs]
+    ref, rinfo, rcode = _run(lib, [pr["S"] for pr in probs], LAMS, TOL, MAXIT)
+    pw = [6 if p >= 48 else 1 for p in ps]
+    pc = [3 if p >= 48 else 1 for p in ps]
+    assert any(c > 1 for c in pc)
+    got, infos, code = _run(lib, [pr["S"] for pr in probs], LAMS, TOL, MAXIT,
+                            problem_workgroups=pw, problem_col_slices=pc, block_threads=threads,
+                            cols_per_lane=cpl)
+    assert code == rcode
+    for b in range(len(probs)):
+        assert infos[b][0]["row_groups"] * infos[b][0]["col_slices"] == pw[b]
+        assert infos[b][0]["col_slices"] == pc[b]
+        for l in range(len(LAMS)):
+            assert np.array_equal(got[b][l], ref[b][l]), (b, l)
+            assert infos[b][l]["sweeps"] == rinfo[b][l]["sweeps"]
+            assert infos[b][l]["nnz_upper"] == rinfo[b][l]["nnz_upper"]
+    # slices that do not divide a problem's workgroups are rejected
+    _, _, bad = _run(lib, [pr["S"] for pr in probs], LAMS, TOL, MAXIT, problem_workgroups=pw,
+                     problem_col_slices=[4 if c > 1 else 1 for c in pc])
+    assert bad == -1
+    _, _, bad = _run(lib, [pr["S"] for pr in probs], LAMS, TOL, MAXIT, cols_per_lane=3)
+    assert bad == -1
