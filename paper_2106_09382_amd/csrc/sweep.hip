@@ -10,7 +10,7 @@ size_t sweep_lds_bytes(const SweepParams<T> &P)
     size_t bytes = sizeof(T) * ((size_t)P.nr_max * P.depth + 16);
     if (P.w_lds)
         bytes += sizeof(T) * (size_t)P.nr_max * P.nc_max;
-    bytes += sizeof(int) * ((size_t)P.nr_max * P.depth + 2 * (size_t)P.nr_max + 5);
+    bytes += sizeof(int) * ((size_t)P.nr_max * P.depth + 2 * (size_t)P.nr_max + 8);
     bytes += sizeof(unsigned) * 16;
     bytes += 8 + sizeof(double) * 16 + sizeof(unsigned long long) * 16;  // path summaries
     return bytes;

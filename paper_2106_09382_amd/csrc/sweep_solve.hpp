@@ -231,6 +231,14 @@ __device__ void flush_rows(const int *rows, int nrows, const int *pj, const T *p
                     v[q] = fma(d, sv[e][q], v[q]);
             }
         }
+        // Every load of this unit has been consumed (so this wait costs
+        // nothing); stating it lets the compiler's wait analysis see that no
+        // load of the rewrite is still in flight after it, on any path.
+        // Otherwise the first LDS read after the step's barrier waits for
+        // every load in flight, including the next step's prefetched
+        // operands.  (s_waitcnt vmcnt(0); expcnt and lgkmcnt left at their
+        // maxima.)
+        __builtin_amdgcn_s_waitcnt(0x0F70);
 #pragma unroll
         for (int q = 0; q < CPL; ++q)
             if (cl + 64 * q < nc)
@@ -443,7 +451,8 @@ __device__ void pcd_solve(const SweepParams<T> &P, int g, int G, unsigned char *
     int *flist = np + NR;                       // rows to rewrite this step
     int *nflush = flist + NR;                   // [3] counters, by step mod 3; [3] spare
     int *s_fail = nflush + 4;
-    unsigned *ured = reinterpret_cast<unsigned *>(s_fail + 1);  // 16 wave partials
+    int *sfail3 = s_fail + 1;                   // [3] a wait of the step failed, by step mod 3
+    unsigned *ured = reinterpret_cast<unsigned *>(sfail3 + 3);  // 16 wave partials
     double *dred = reinterpret_cast<double *>(((uintptr_t)(ured + 16) + 7) & ~(uintptr_t)7);
     unsigned long long *nred = reinterpret_cast<unsigned long long *>(dred + 16);
 
@@ -466,6 +475,9 @@ __device__ void pcd_solve(const SweepParams<T> &P, int g, int G, unsigned char *
         nflush[2] = 0;
         nflush[3] = 0;
         *s_fail = 0;
+        sfail3[0] = 0;
+        sfail3[1] = 0;
+        sfail3[2] = 0;
     }
     if (WLDS) {
         for (long e = tid; e < (long)nr * nc; e += nthr) {
@@ -616,6 +628,7 @@ __device__ void pcd_solve(const SweepParams<T> &P, int g, int G, unsigned char *
                 }
                 if (lfail) {
                     *s_fail = 1;
+                    sfail3[s3] = 1;
                     continue;
                 }
 
@@ -758,22 +771,29 @@ __device__ void pcd_solve(const SweepParams<T> &P, int g, int G, unsigned char *
                                              P.jo_S);
             }
 
-            // ---- every row of the step is done; rewrite the rows whose lists are full
-            const int any = __syncthreads_or(lfail | marked);
-            if (tid == 0)
-                nflush[(s3 + 2) % 3] = 0;  // counter of the previous step, read by all by now
+            // ---- every row of the step is done; rewrite the rows whose lists are full.
+            // The step's outcome (rows to rewrite, a failed wait) is in LDS words
+            // kept by step mod 3, read after a plain barrier.  A block-wide vote
+            // here would wait for every load the wave has in flight, i.e. for
+            // the operands just prefetched for the next step, before the
+            // rewrites could issue their own loads; this way the two overlap.
+            __syncthreads();
+            const int nf = nflush[s3];
+            const int sf = sfail3[s3];
+            if (tid == 0) {
+                // the previous step's words, read by all by now
+                nflush[(s3 + 2) % 3] = 0;
+                sfail3[(s3 + 2) % 3] = 0;
+            }
             if (ts)
                 ts[1] = __builtin_amdgcn_s_memrealtime();
-            if (any) {
-                if (*s_fail) {
-                    failed = 1;
-                    break;
-                }
-                const int nf = nflush[s3];
-                if (nf > 0) {
-                    flush_rows<T, WLDS, CPL>(flist, nf, pj, pdl, np, D, a, Gr, p, c0, nc, S, Wg, wblk);
-                    __syncthreads();
-                }
+            if (sf) {
+                failed = 1;
+                break;
+            }
+            if (nf > 0) {
+                flush_rows<T, WLDS, CPL>(flist, nf, pj, pdl, np, D, a, Gr, p, c0, nc, S, Wg, wblk);
+                __syncthreads();
             }
             if (ts)
                 ts[2] = __builtin_amdgcn_s_memrealtime();
