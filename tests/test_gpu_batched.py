@@ -284,8 +284,11 @@ def test_config4_full_batch_properties(lib, config4):
 def test_config4_smallest_problems_match_the_oracle_along_their_paths(lib, config4):
     # The three smallest problems of the batch (p = 254, 261, 274), every
     # lambda of their paths, against the FP64 oracle on the Gram of the same
-    # (FP32-rounded) draws with the FP32 stopping rule: within 1e-4, the same
-    # support outside borderline pairs (1e-4), on the lambdas both converged.
+    # (FP32-rounded) draws with the FP32 stopping rule, on the lambdas both
+    # converged: within 1e-4 relative to the largest entry of Omega (reading
+    # R23: FP32 error scales with the entries, which grow to about 4.5 at the
+    # end of the path, where n = p/2 makes the sweeps contract slowly), the
+    # same support outside the pairs borderline at that scale.
     c = config4
     probs, lams, tol, maxit = c["probs"], c["lams"], c["tol"], c["maxit"]
     order = np.argsort([pr["p"] for pr in probs])
@@ -303,9 +306,12 @@ def test_config4_smallest_problems_match_the_oracle_along_their_paths(lib, confi
                 continue
             checked += 1
             got = c["outs"][b][l].double().cpu().numpy()
+            scale = max(1.0, float(np.abs(om).max()))
             err = np.abs(got - om).max()
-            assert err <= 1e-4, (b, l, pr["p"], err)
-            assert _support_mismatch(S, got, om, lam, 1e-4) == 0, (b, l)
+            print(f"  lambda {lam:.4f}: sweeps gpu {gi['sweeps']} oracle {winfo['sweeps']}, "
+                  f"max|Omega| {scale:.3f}, max error {err:.3e}", flush=True)
+            assert err <= 1e-4 * scale, (b, l, pr["p"], err, scale)
+            assert _support_mismatch(S, got, om, lam, 1e-4 * scale) == 0, (b, l)
     assert checked >= 0.8 * total
 
 
