@@ -30,6 +30,7 @@
 #ifndef CONCORD_H
 #define CONCORD_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -47,7 +48,8 @@ enum {
     CONCORD_ENOTPD = -3,       /* some S_ii <= 0: eq. (2) and eq. (3) divide by S_ii */
     CONCORD_ENOMEM = -4,       /* workspace allocation failed */
     CONCORD_EDEVICE = -5,      /* HIP runtime error, or a device wait ran past its bound */
-    CONCORD_ELAUNCH = -6       /* launch shape cannot be made co-resident on this device */
+    CONCORD_ELAUNCH = -6,      /* launch shape cannot be made co-resident on this device */
+    CONCORD_ESCRATCH = -7      /* concord_fit_noalloc: workspace larger than its fixed scratch */
 };
 
 /* Result of one solve. */
@@ -121,6 +123,34 @@ typedef struct {
 int concord_fit(concord_input kind, const void *X, int64_t n, int64_t p, double lambda,
                 double tol, int32_t maxit, concord_dtype dt, const void *omega0, void *omega,
                 concord_info *info, void *stream);
+
+/* Bytes of the fixed device scratch that concord_fit_noalloc works in. */
+#define CONCORD_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/*
+ * concord_fit_noalloc -- concord_fit for callers that cannot allocate device
+ * memory (code under stream capture, serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, same kernels and launch shape, same results
+ * bit for bit.  The workspace (W = Omega S, the sweep layout of Omega, the
+ * published entries, barrier and reduction words, and S itself when the
+ * input is Y) is carved from one fixed array of CONCORD_NOALLOC_SCRATCH_BYTES
+ * in device memory, which every device the library runs on holds from its
+ * first call there until the process ends.  The call allocates no device
+ * memory and creates no events: info's device times (elapsed_ms, gram_ms,
+ * sweep_ms) read 0.  Everything the solve needs zeroed is cleared by its own
+ * kernels, so a call never depends on what the previous one left.
+ *   Returns CONCORD_ESCRATCH, before any device work, when the solve needs
+ *   more than the scratch.  With the default launch shape on a 256-CU
+ *   device that allows p <= 1280 from S and p <= 1152 from Y in FP64,
+ *   p <= 1792 and p <= 1664 in FP32.
+ * All calls on one device share its scratch: calls that overlap in time on
+ * the same device (two host threads, or two streams) race and must be
+ * serialised by the caller.  The call still synchronises `stream` before
+ * returning, as concord_fit does.
+ */
+int concord_fit_noalloc(concord_input kind, const void *X, int64_t n, int64_t p, double lambda,
+                        double tol, int32_t maxit, concord_dtype dt, const void *omega0,
+                        void *omega, concord_info *info, void *stream);
 
 /* concord_fit with explicit launch options (opts may be NULL = defaults). */
 int concord_fit_ex(concord_input kind, const void *X, int64_t n, int64_t p, double lambda,

@@ -19,7 +19,8 @@ LIB_PATH = os.path.join(HERE, "libconcord.so")
 F32, F64 = 0, 1
 INPUT_S, INPUT_Y = 0, 1
 OK, NOT_CONVERGED = 0, 1
-EINVAL, ENONFINITE, ENOTPD, ENOMEM, EDEVICE, ELAUNCH = -1, -2, -3, -4, -5, -6
+EINVAL, ENONFINITE, ENOTPD, ENOMEM, EDEVICE, ELAUNCH, ESCRATCH = -1, -2, -3, -4, -5, -6, -7
+NOALLOC_SCRATCH_BYTES = 64 << 20  # CONCORD_NOALLOC_SCRATCH_BYTES
 
 
 class ConcordInfo(ctypes.Structure):
@@ -130,6 +131,8 @@ def load(path: str = LIB_PATH):
     lib.concord_fit.argtypes = [ctypes.c_int, vp, i64, i64, dbl, dbl, i32, ctypes.c_int, vp, vp,
                                 ctypes.POINTER(ConcordInfo), vp]
     lib.concord_fit.restype = ctypes.c_int
+    lib.concord_fit_noalloc.argtypes = lib.concord_fit.argtypes
+    lib.concord_fit_noalloc.restype = ctypes.c_int
     lib.concord_fit_ex.argtypes = lib.concord_fit.argtypes + [ctypes.POINTER(ConcordOptions)]
     lib.concord_fit_ex.restype = ctypes.c_int
     lib.concord_fit_batched_ex.argtypes = [
@@ -259,6 +262,50 @@ def fit(X: torch.Tensor, lam: float, tol: float = 1e-6, maxit: int = 500, *, kin
         d["delta_trace"] = [tr[k] for k in range(max(0, info.sweeps))]
     if check:
         _raise(code, "concord_fit")
+    return out, d
+
+
+def fit_noalloc(X: torch.Tensor, lam: float, tol: float = 1e-6, maxit: int = 500, *,
+                kind: str = "S", omega0: torch.Tensor | None = None,
+                out: torch.Tensor | None = None, stream=None, check: bool = True):
+    """concord_fit_noalloc: one solve in the library's fixed device scratch
+    (no device allocation inside the call).  ``out`` must be given by callers
+    that cannot allocate; otherwise it is allocated here, before the call.
+    Returns (omega, info dict); the device times in info read 0."""
+    lib = load()
+    _check_dev(X, "X")
+    dt = _dtype_code(X)
+    if kind == "S":
+        if X.dim() != 2 or X.shape[0] != X.shape[1]:
+            raise ValueError("S must be square")
+        p, n, kc = X.shape[0], 0, INPUT_S
+    elif kind == "Y":
+        if X.dim() != 2:
+            raise ValueError("Y must be a matrix")
+        n, p, kc = X.shape[0], X.shape[1], INPUT_Y
+    else:
+        raise ValueError("kind must be 'S' or 'Y'")
+    if out is None:
+        out = torch.empty((p, p), dtype=X.dtype, device=X.device)
+    _check_dev(out, "out")
+    if out.dtype != X.dtype or tuple(out.shape) != (p, p):
+        raise ValueError("out must be p x p with X's dtype")
+    o0 = None
+    if omega0 is not None:
+        _check_dev(omega0, "omega0")
+        if omega0.dtype != X.dtype or tuple(omega0.shape) != (p, p):
+            raise ValueError("omega0 must be p x p with X's dtype")
+        o0 = ctypes.c_void_p(omega0.data_ptr())
+    info = ConcordInfo()
+    with torch.cuda.device(X.device):
+        code = lib.concord_fit_noalloc(kc, ctypes.c_void_p(X.data_ptr()), n, p, float(lam),
+                                       float(tol), int(maxit), dt, o0,
+                                       ctypes.c_void_p(out.data_ptr()), ctypes.byref(info),
+                                       _stream_handle(stream))
+    d = info.as_dict()
+    d["code"] = code
+    if check:
+        _raise(code, "concord_fit_noalloc")
     return out, d
 
 

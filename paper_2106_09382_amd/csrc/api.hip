@@ -9,6 +9,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "../../include/concord.h"
@@ -165,6 +166,35 @@ int map_hip(hipError_t e)
             return map_hip(e_);              \
     } while (0)
 
+// Fixed device workspace of concord_fit_noalloc.  Each device the library
+// runs on holds its own copy from its first use until the process ends.  In
+// host code `scratch` names a host-side stand-in, not device memory: only the
+// address that hipGetSymbolAddress returns for the current device is passed
+// to kernels.
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[CONCORD_NOALLOC_SCRATCH_BYTES];
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];
+
+// Device address of `scratch` on the current device (looked up once per device).
+int scratch_address(void **out)
+{
+    int dev = -1;
+    CK_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices)
+        return CONCORD_EDEVICE;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        CK_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr)
+            return CONCORD_EDEVICE;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return CONCORD_OK;
+}
+
 // Greedy edge colouring of the support (edges i < j, in any order): edges in
 // lexicographic order each take the smallest colour neither endpoint has
 // used.  Writes the m x p partner table (part[c * p + i] = partner of i in
@@ -209,10 +239,16 @@ int greedy_colouring(const int *edges, int ne, int p, std::vector<int> *part)
     return m;
 }
 
+// ext_ws == nullptr: the workspace is allocated stream-ordered and freed
+// before returning, and the call is timed with events.  Otherwise the
+// workspace is carved from ext_ws (ext_cap bytes of device memory that the
+// caller keeps), nothing is allocated and no events are created (the times
+// in info read 0).
 template <typename T>
 int fit_impl(concord_input kind, const void *X, int64_t n64, int64_t p64, double lambda,
              double tol, int32_t maxit, const void *omega0, void *omega, concord_info *info,
-             hipStream_t stream, const concord_options *opts)
+             hipStream_t stream, const concord_options *opts, void *ext_ws = nullptr,
+             size_t ext_cap = 0)
 {
     const int p = (int)p64, n = (int)n64;
     Shape sh;
@@ -234,9 +270,11 @@ int fit_impl(concord_input kind, const void *X, int64_t n64, int64_t p64, double
                     (void)hipEventDestroy(e[k]);
         }
     } evg{ev};
-    for (int k = 0; k < 6; ++k)
-        CK_HIP(hipEventCreate(&ev[k]));
-    CK_HIP(hipEventRecord(ev[0], stream));
+    const bool own_ws = (ext_ws == nullptr);
+    if (own_ws)
+        for (int k = 0; k < 6; ++k)
+            CK_HIP(hipEventCreate(&ev[k]));
+    auto rec = [&](int k) { return ev[k] ? hipEventRecord(ev[k], stream) : hipSuccess; };
 
     // Workspace layout.
     Carver cv;
@@ -272,14 +310,17 @@ int fit_impl(concord_input kind, const void *X, int64_t n64, int64_t p64, double
     Workspace ws;
     ws.stream = stream;
     ws.bytes = cv.off;
-    {
+    if (own_ws) {
         hipError_t e = hipMallocAsync(&ws.base, ws.bytes, stream);
         if (e != hipSuccess) {
             ws.base = nullptr;
             return map_hip(e);
         }
+    } else if (cv.off > ext_cap) {
+        return CONCORD_ESCRATCH;
     }
-    char *B = (char *)ws.base;
+    char *B = own_ws ? (char *)ws.base : (char *)ext_ws;
+    CK_HIP(rec(0));
     T *S = (kind == CONCORD_INPUT_Y) ? (T *)(B + oS) : (T *)X;
     T *W = (T *)(B + oW);
     T *omp = (T *)(B + oOmp), *omdp = (T *)(B + oOmdp), *sd = (T *)(B + oSd);
@@ -292,9 +333,9 @@ int fit_impl(concord_input kind, const void *X, int64_t n64, int64_t p64, double
 
     CK_HIP(launch_clear(flags, G, red, 4 * maxit, out, kOutWords, acc, 4, stream));
     if (kind == CONCORD_INPUT_Y) {
-        CK_HIP(hipEventRecord(ev[2], stream));
+        CK_HIP(rec(2));
         CK_HIP(launch_gram<T>((const T *)X, n, p, S, stream));
-        CK_HIP(hipEventRecord(ev[3], stream));
+        CK_HIP(rec(3));
     }
     CK_HIP(launch_check_copy<T>(S, p, W, omega0 == nullptr, sd, out + 4, stream));
     if (omega0)
@@ -330,7 +371,7 @@ int fit_impl(concord_input kind, const void *X, int64_t n64, int64_t p64, double
     P.spin_limit = kSpinLimit;
     P.tstamp = opts ? reinterpret_cast<unsigned long long *>(opts->device_timestamps) : nullptr;
     P.tstamp_steps = (opts && opts->device_timestamps) ? opts->timestamp_steps : 0;
-    CK_HIP(hipEventRecord(ev[4], stream));
+    CK_HIP(rec(4));
     // active-set bookkeeping (host): reductions of the full sweeps, moves of
     // all launches, active sweeps
     std::vector<unsigned long long> full_red;
@@ -417,12 +458,12 @@ int fit_impl(concord_input kind, const void *X, int64_t n64, int64_t p64, double
         P.part = nullptr;
         CK_HIP(launch_clear(nullptr, 0, nullptr, 0, nullptr, 0, acc, 4, stream));
     }
-    CK_HIP(hipEventRecord(ev[5], stream));
+    CK_HIP(rec(5));
     CK_HIP(launch_finalize<T>(omp, omdp, sh.Gr, sh.Gc, sh.nr_max, W, p, (T)lambda, (T *)omega, acc,
                               nnz, out + 4, stream));
     if (opts && opts->w_out)
         CK_HIP(hipMemcpyAsync(opts->w_out, W, sizeof(T) * pp, hipMemcpyDeviceToDevice, stream));
-    CK_HIP(hipEventRecord(ev[1], stream));
+    CK_HIP(rec(1));
 
     // One readback: status words, summary accumulators and the per-sweep
     // reductions (2 * maxit words, a few KB).
@@ -437,10 +478,12 @@ int fit_impl(concord_input kind, const void *X, int64_t n64, int64_t p64, double
                           hipMemcpyDeviceToHost, stream));
     CK_HIP(hipStreamSynchronize(stream));
     float ms = 0.f, ms_gram = 0.f, ms_sweep = 0.f;
-    (void)hipEventElapsedTime(&ms, ev[0], ev[1]);
-    if (kind == CONCORD_INPUT_Y)
-        (void)hipEventElapsedTime(&ms_gram, ev[2], ev[3]);
-    (void)hipEventElapsedTime(&ms_sweep, ev[4], ev[5]);
+    if (own_ws) {
+        (void)hipEventElapsedTime(&ms, ev[0], ev[1]);
+        if (kind == CONCORD_INPUT_Y)
+            (void)hipEventElapsedTime(&ms_gram, ev[2], ev[3]);
+        (void)hipEventElapsedTime(&ms_sweep, ev[4], ev[5]);
+    }
 
     auto bits_to = [](unsigned long long u) -> double {
         if (sizeof(T) == 8) {
@@ -1352,6 +1395,36 @@ extern "C" int concord_fit(concord_input kind, const void *X, int64_t n, int64_t
                           nullptr);
 }
 
+extern "C" int concord_fit_noalloc(concord_input kind, const void *X, int64_t n, int64_t p,
+                                   double lambda, double tol, int32_t maxit, concord_dtype dt,
+                                   const void *omega0, void *omega, concord_info *info,
+                                   void *stream)
+{
+    int rc = validate(kind, X, n, p, lambda, tol, maxit, dt, omega);
+    void *ws = nullptr;
+    if (!rc)
+        rc = scratch_address(&ws);
+    if (rc) {
+        if (info) {
+            memset(info, 0, sizeof(*info));
+            info->status = rc;
+        }
+        return rc;
+    }
+    if (info)
+        memset(info, 0, sizeof(*info));  // an early error return leaves only the status
+    hipStream_t st = (hipStream_t)stream;
+    const size_t cap = CONCORD_NOALLOC_SCRATCH_BYTES;
+    rc = (dt == CONCORD_F64)
+             ? fit_impl<double>(kind, X, n, p, lambda, tol, maxit, omega0, omega, info, st,
+                                nullptr, ws, cap)
+             : fit_impl<float>(kind, X, n, p, lambda, tol, maxit, omega0, omega, info, st,
+                               nullptr, ws, cap);
+    if (rc < 0 && info && info->status == 0)
+        info->status = rc;
+    return rc;
+}
+
 extern "C" int concord_fit_joint_ex(concord_input kind, const void *X1, const void *X2,
                                     int64_t n1, int64_t n2, int64_t p, double lambda1,
                                     double lambda2, double tol, int32_t maxit, concord_dtype dt,
@@ -1504,6 +1577,9 @@ extern "C" const char *concord_strerror(int code)
     case CONCORD_ENOMEM: return "device workspace allocation failed";
     case CONCORD_EDEVICE: return "HIP runtime error or a device wait exceeded its bound";
     case CONCORD_ELAUNCH: return "launch shape cannot be made co-resident on this device";
+    case CONCORD_ESCRATCH:
+        return "the solve needs more workspace than concord_fit_noalloc's fixed scratch "
+               "(CONCORD_NOALLOC_SCRATCH_BYTES)";
     default: return "unknown status code";
     }
 }

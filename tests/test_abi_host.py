@@ -57,7 +57,7 @@ def test_schedule_rejects_bad_p(lib):
 
 
 def test_strerror_covers_codes(lib):
-    for c in (0, 1, -1, -2, -3, -4, -5, -6):
+    for c in (0, 1, -1, -2, -3, -4, -5, -6, -7):
         s = lib.concord_strerror(c).decode()
         assert s and s != "unknown status code"
     assert lib.concord_strerror(99).decode() == "unknown status code"
@@ -84,6 +84,34 @@ def _fit(lib, **kw):
 def test_invalid_arguments_return_einval(lib, kw):
     rc, info = _fit(lib, **kw)
     assert rc == -1 and info.status == -1
+
+
+@pytest.mark.parametrize("kw", [
+    dict(X=None), dict(omega=None), dict(p=0), dict(p=50000), dict(lam=-0.1),
+    dict(tol=0.0), dict(maxit=0), dict(dt=7), dict(kind=5), dict(kind=1, n=0),
+])
+def test_noalloc_invalid_arguments_return_einval(lib, kw):
+    """concord_fit_noalloc checks its arguments as concord_fit does, before
+    it looks up its scratch on the device."""
+    from paper_2106_09382_amd import _lib
+    a = dict(kind=0, X=ctypes.c_void_p(0x1000), n=0, p=8, lam=0.1, tol=1e-6, maxit=10, dt=1,
+             omega0=None, omega=ctypes.c_void_p(0x2000))
+    a.update(kw)
+    info = _lib.ConcordInfo()
+    info.sweeps = 77
+    rc = lib.concord_fit_noalloc(a["kind"], a["X"], a["n"], a["p"], a["lam"], a["tol"],
+                                 a["maxit"], a["dt"], a["omega0"], a["omega"],
+                                 ctypes.byref(info), None)
+    assert rc == -1 and info.status == -1 and info.sweeps == 0
+
+
+def test_noalloc_scratch_size_matches_the_header():
+    from paper_2106_09382_amd import _lib
+    text = open(HEADER).read()
+    m = re.search(r"#define CONCORD_NOALLOC_SCRATCH_BYTES \(\(size_t\)(\d+) << (\d+)\)", text)
+    assert m, "CONCORD_NOALLOC_SCRATCH_BYTES not found"
+    assert int(m.group(1)) << int(m.group(2)) == _lib.NOALLOC_SCRATCH_BYTES
+    assert "CONCORD_ESCRATCH = -7" in text and _lib.ESCRATCH == -7
 
 
 @pytest.mark.parametrize("rows,cols,threads", [(32, 8, 512), (16, 16, 256), (1, 1, 64)])
