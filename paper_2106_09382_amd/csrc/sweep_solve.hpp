@@ -254,6 +254,7 @@ __device__ void flush_rows(const int *rows, int nrows, const int *pj, const T *p
 template <typename T, bool JNT>
 struct RowJoint {
     T wo, odo, s_jio;
+    T sdo_lo, sdo_hi, sio;  // the other population's S_ii, S_jj and (last colour) S_ii
 };
 template <typename T>
 struct RowJoint<T, false> {
@@ -267,6 +268,8 @@ struct RowNext : RowJoint<T, JNT> {
     bool last;    // the step is the last colour (diagonal step follows)
     bool pubd;    // the step publishes W_ii for the following last colour
     T w, od, s_ji, wb, s_jn, s_in;
+    T sd_lo, sd_hi;  // S_ll and S_hh of the pair (l < h), whose sum is eq. (3)'s denominator
+    T sii;        // S_ii, for the diagonal step after the last colour
     T g;          // adjoint mode: right-hand side of the pair (NaN: pair not free)
     T sv[kMaxDepth];
 };
@@ -279,7 +282,8 @@ __device__ __forceinline__ void load_next(RowNext<T, JNT> &x, const Circle &C, c
                                           const T *__restrict__ Wg, const T *wblk,
                                           const T *__restrict__ omp, const T *__restrict__ omdp,
                                           const T *__restrict__ adjg, const T *omp_o,
-                                          const T *omdp_o, const T *So)
+                                          const T *omdp_o, const T *So,
+                                          const T *__restrict__ sd, const T *sdo)
 {
     // the schedule: Algorithm 1's round robin, or a given colouring's table
     const int m = TAB ? mt : C.m;
@@ -300,10 +304,19 @@ __device__ __forceinline__ void load_next(RowNext<T, JNT> &x, const Circle &C, c
     x.g = (adjg && x.j >= 0) ? adjg[(size_t)r1 * NR + k] : T(0);
     x.od = x.last ? omdp[k] : T(0);
     x.s_ji = (x.j >= 0 && (x.last || x.pubd)) ? S[(size_t)x.j * p + i] : T(0);
+    // the diagonal of S for the step's denominators: loaded here, summed after
+    // the poll (a sum here would wait for these loads at the end of this step)
+    const int lo = (x.j >= 0 && x.j < i) ? x.j : i, hi = (x.j >= 0 && x.j < i) ? i : x.j;
+    x.sd_lo = (x.j >= 0) ? sd[lo] : T(0);
+    x.sd_hi = (x.j >= 0) ? sd[hi] : T(0);
+    x.sii = x.last ? sd[i] : T(0);
     if constexpr (JNT) {
         x.wo = (x.j >= 0) ? omp_o[(size_t)r1 * NR + k] : T(0);
         x.odo = x.last ? omdp_o[k] : T(0);
         x.s_jio = (x.j >= 0 && x.last) ? So[(size_t)x.j * p + i] : T(0);
+        x.sdo_lo = (x.j >= 0) ? sdo[lo] : T(0);
+        x.sdo_hi = (x.j >= 0) ? sdo[hi] : T(0);
+        x.sio = x.last ? sdo[i] : T(0);
     }
     if (x.kn >= 0) {
         x.wb = WLDS ? wblk[(size_t)k * nc + (x.kn - c0)] : Wg[(size_t)i * p + x.kn];
@@ -499,7 +512,7 @@ __device__ void pcd_solve(const SweepParams<T> &P, int g, int G, unsigned char *
         if (k < nr)
             load_next<T, WLDS, TAB, JNT>(nx[u], C, P.part, m, 0, a + k * Gr, k, 0, pj, D, NR, p,
                                          c0, c1, nc, S, Wg, wblk, omp, omdp, adjg, omp_o, omdp_o,
-                                         P.jo_S);
+                                         P.jo_S, sd, P.jo_sd);
     }
     // adjoint mode: the diagonal right-hand side and denominator of each row
     T adj_gd[RPT], adj_hd[RPT];
@@ -576,6 +589,47 @@ __device__ void pcd_solve(const SweepParams<T> &P, int g, int G, unsigned char *
                 const RowNext<T, JNT> &x = nx[u];
                 const int j = x.j;
 
+                // ---- poll the published numerator entries of this colour.  The
+                // first poll is issued before anything waits for the operands
+                // prefetched last step: issued after that wait, the poll's round
+                // trip would follow the prefetch's instead of overlapping it.
+                U blo = 0, bhi = 0, bd = 0, clo = 0, chi = 0, cd = 0;
+                // slots of row i (own, contiguous over k) and of its partner
+                const int si = a * NR + k;
+                const int sj = (j >= 0) ? (j % Gr) * NR + j / Gr : 0;
+                const int lo = (j >= 0 && j < i) ? sj : si, hi = (j >= 0 && j < i) ? si : sj;
+                const bool poll_d = last && m >= 2;
+                auto issue_poll = [&]() {
+                    if (j >= 0) {
+                        blo = ld_dev(&pcu[lo]);
+                        bhi = ld_dev(&pcu[hi]);
+                        if constexpr (JNT) {
+                            clo = ld_dev(&pco[lo]);
+                            chi = ld_dev(&pco[hi]);
+                        }
+                    }
+                    if (last) {
+                        bd = ld_dev(&pdu[si]);
+                        if constexpr (JNT)
+                            cd = ld_dev(&pdo[si]);
+                    }
+                };
+                auto polled = [&]() {
+                    bool ok = true;
+                    if (j >= 0) {
+                        ok = (blo != SENT) && (bhi != SENT);
+                        if constexpr (JNT)
+                            ok = ok && (clo != SENT) && (chi != SENT);
+                    }
+                    if (last) {
+                        ok = ok && (!poll_d || bd != SENT);
+                        if constexpr (JNT)
+                            ok = ok && (!poll_d || cd != SENT);
+                    }
+                    return ok;
+                };
+                issue_poll();
+
                 // ---- stored entries plus pending updates, for what this step publishes
                 T vpre = T(0), vdpre = T(0);
                 if (x.kn >= 0) {
@@ -585,37 +639,10 @@ __device__ void pcd_solve(const SweepParams<T> &P, int g, int G, unsigned char *
                         if (e < x.n)
                             vpre = fma(pdl[k * D + e], x.sv[e], vpre);
                 }
-                // ---- wait for the published numerator entries of this colour
-                U blo = 0, bhi = 0, bd = 0, clo = 0, chi = 0, cd = 0;
+                // ---- wait for the polled entries, polling again until they are there
                 {
-                    // slots of row i (own, contiguous over k) and of its partner
-                    const int si = a * NR + k;
-                    const int sj = (j >= 0) ? (j % Gr) * NR + j / Gr : 0;
-                    const int lo = (j >= 0 && j < i) ? sj : si, hi = (j >= 0 && j < i) ? si : sj;
-                    const bool poll_d = last && m >= 2;
                     long long spins = 0;
-                    for (;;) {
-                        bool ok = true;
-                        if (j >= 0) {
-                            blo = ld_dev(&pcu[lo]);
-                            bhi = ld_dev(&pcu[hi]);
-                            ok = (blo != SENT) && (bhi != SENT);
-                            if constexpr (JNT) {
-                                clo = ld_dev(&pco[lo]);
-                                chi = ld_dev(&pco[hi]);
-                                ok = ok && (clo != SENT) && (chi != SENT);
-                            }
-                        }
-                        if (last) {
-                            bd = ld_dev(&pdu[si]);
-                            ok = ok && (!poll_d || bd != SENT);
-                            if constexpr (JNT) {
-                                cd = ld_dev(&pdo[si]);
-                                ok = ok && (!poll_d || cd != SENT);
-                            }
-                        }
-                        if (ok)
-                            break;
+                    while (!polled()) {
                         ++spins;
                         if (spins > P.spin_limit ||
                             ((spins & 255) == 0 && ld_dev(&P.out[3]) != 0)) {
@@ -624,6 +651,7 @@ __device__ void pcd_solve(const SweepParams<T> &P, int g, int G, unsigned char *
                             break;
                         }
                         __builtin_amdgcn_s_sleep(1);
+                        issue_poll();
                     }
                 }
                 if (lfail) {
@@ -645,19 +673,23 @@ __device__ void pcd_solve(const SweepParams<T> &P, int g, int G, unsigned char *
                     vdpre = WLDS ? wblk[(size_t)k * nc + (i - c0)] : Wg[(size_t)i * p + i];
                     for (int e = 0; e < n0; ++e)
                         vdpre = fma(pdl[k * D + e], S[(size_t)pj[k * D + e] * p + i], vdpre);
+                    // every load of this once-per-sweep fold is consumed; said
+                    // explicitly so that the compiler's wait analysis does not
+                    // carry them into the next step, whose first register
+                    // writes would then wait for every load in flight
+                    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
                 }
 
                 // ---- eq. (3) for the pair, eq. (2) after the last colour
                 T del = T(0), dd = T(0);
                 T del_o = T(0), dd_o = T(0);  // joint mode: the other population's changes
                 if (j >= 0) {
-                    const int lo = j < i ? j : i, hi = j < i ? i : j;
-                    const T sden = sd[lo] + sd[hi];
+                    const T sden = x.sd_lo + x.sd_hi;
                     const T bnum = fma(-sden, x.w, as_value<T>(blo) + as_value<T>(bhi));
                     T wn;
                     if constexpr (JNT) {
                         // the block update takes population 1's operands first on both sides
-                        const T sden_o = P.jo_sd[lo] + P.jo_sd[hi];
+                        const T sden_o = x.sdo_lo + x.sdo_hi;
                         const T bnum_o = fma(-sden_o, x.wo, as_value<T>(clo) + as_value<T>(chi));
                         T x1, x2;
                         if (P.pop == 0)
@@ -682,14 +714,14 @@ __device__ void pcd_solve(const SweepParams<T> &P, int g, int G, unsigned char *
                     T wii = as_value<T>(bd);
                     if (del != T(0))
                         wii = fma(del, x.s_ji, wii);
-                    const T sii = sd[i];
+                    const T sii = x.sii;
                     const T c = fma(-sii, x.od, wii);
                     T on;
                     if constexpr (JNT) {
                         T wio = as_value<T>(cd);
                         if (del_o != T(0))
                             wio = fma(del_o, x.s_jio, wio);
-                        const T sio = P.jo_sd[i];
+                        const T sio = x.sio;
                         const T co = fma(-sio, x.odo, wio);
                         T y1, y2;
                         if (P.pop == 0)
@@ -768,7 +800,7 @@ __device__ void pcd_solve(const SweepParams<T> &P, int g, int G, unsigned char *
                 // workgroup barrier below), so it is folded with all n entries.
                 load_next<T, WLDS, TAB, JNT>(nx[u], C, P.part, m, rn, i, k, n, pj, D, NR, p, c0,
                                              c1, nc, S, Wg, wblk, omp, omdp, adjg, omp_o, omdp_o,
-                                             P.jo_S);
+                                             P.jo_S, sd, P.jo_sd);
             }
 
             // ---- every row of the step is done; rewrite the rows whose lists are full.
