@@ -88,8 +88,10 @@ def search(run, ps, total: int, threads: int = 512, cpls=(4, 2), slice_options=(
 
     1. runs the built-in plan and deals the workgroups by its measured work;
     2. for each candidate number of column slices, deals the workgroups
-       again in multiples of it, runs every problem large enough with that
-       split and keeps, problem by problem, the split with the smaller work
+       again in multiples of it, runs the problems large enough with that
+       split (the heaviest first, while every problem's minimum count still
+       fits the launch) and keeps, problem by problem, the split with the
+       smaller work
        (device time x workgroups, so that problems whose counts moved are
        compared fairly);
     3. re-deals the workgroups by the work measured at the chosen splits,
@@ -116,12 +118,18 @@ def search(run, ps, total: int, threads: int = 512, cpls=(4, 2), slice_options=(
     G = plan_from_infos(ps, infos, total, threads)
     C = [1] * B
     infos, wall = trial("dealt by measured work", G, C, cpl0)
-    best = {"problem_workgroups": G, "problem_col_slices": C, "cols_per_lane": cpl0,
+    best = {"problem_workgroups": list(G), "problem_col_slices": list(C), "cols_per_lane": cpl0,
             "wall_s": wall}
     work = problem_work(infos)
     for c in slice_options:
-        # every problem large enough for c slices of at least 8 rows per row group
-        cand = [c if p >= 16 * c else 1 for p in ps]
+        # problems large enough for c slices of at least 8 rows per row group,
+        # the heaviest first, as long as every problem's minimum still fits
+        cand = [1] * B
+        need = sum(min_workgroups(p, threads) for p in ps)
+        for b in sorted(range(B), key=lambda b: -work[b]):
+            extra = min_workgroups(ps[b], threads, c) - min_workgroups(ps[b], threads)
+            if ps[b] >= 16 * c and need + extra <= total:
+                cand[b], need = c, need + extra
         Gc = plan(ps, work, total, threads, cand)
         cand = [x if _slices_ok(p, g, x, threads) else 1 for p, g, x in zip(ps, Gc, cand)]
         if all(x == 1 for x in cand):
@@ -139,8 +147,8 @@ def search(run, ps, total: int, threads: int = 512, cpls=(4, 2), slice_options=(
         infos_f, wall_f = trial(f"re-dealt at the chosen splits, {cpl} columns per lane",
                                 G2, C2, cpl)
         if wall_f < best["wall_s"]:
-            best = {"problem_workgroups": G2, "problem_col_slices": C2, "cols_per_lane": cpl,
-                    "wall_s": wall_f}
+            best = {"problem_workgroups": list(G2), "problem_col_slices": list(C2),
+                    "cols_per_lane": cpl, "wall_s": wall_f}
     best["trials"] = trials
     best["slices_used"] = sorted({int(c) for c in best["problem_col_slices"]})
     best["work_model_exponent"] = _fit_exponent(ps, problem_work(infos))

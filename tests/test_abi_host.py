@@ -210,6 +210,23 @@ def test_autotune_search_keeps_what_measures_faster():
         return infos, max(r[0]["sweep_ms"] for r in infos)
 
     best = autotune.search(run, ps, 64)
+    # a launch too small to give every problem two slices: only the heaviest
+    # is tried with them (minimum 2 workgroups each, 4 with two slices)
+    tried = []
+
+    def run_tight(pw, pc, cpl):
+        tried.append(pc)
+        pw = pw or [2, 2, 3, 4]
+        pc = pc or [1] * 4
+        infos = [[{"sweep_ms": (4.0 if b == 3 else 1.0) / g, "row_groups": g // c,
+                   "col_slices": c}] for b, (g, c) in enumerate(zip(pw, pc))]
+        return infos, max(r[0]["sweep_ms"] for r in infos)
+
+    tight = autotune.search(run_tight, [1500, 1500, 1500, 1500], 11)
+    assert [1, 1, 1, 2] in tried
+    assert sum(tight["problem_workgroups"]) <= 11
+    assert all(g % c == 0 for g, c in zip(tight["problem_workgroups"],
+                                          tight["problem_col_slices"]))
     C = best["problem_col_slices"]
     assert C[2] == 2 and C[3] == 2 and C[0] == 1 and C[1] == 1
     assert best["cols_per_lane"] == 4
@@ -218,6 +235,24 @@ def test_autotune_search_keeps_what_measures_faster():
         assert g % c == 0 and -(-p // (g // c)) <= 1024
     assert best["wall_s"] == min(t["wall_s"] for t in best["trials"])
     assert calls[0] == (None, None, 4) and len(calls) == len(best["trials"])
+    # the plan returned is one that ran, as it ran (no list changed afterwards)
+    assert any(t["problem_workgroups"] == best["problem_workgroups"]
+               and t["problem_col_slices"] == best["problem_col_slices"]
+               and t["cols_per_lane"] == best["cols_per_lane"]
+               and t["wall_s"] == best["wall_s"] for t in best["trials"])
+
+    # a model where the slices lower the large problems' own times but the
+    # batch as a whole runs slower with them: the one-slice plan must come
+    # back exactly as it was run, although the per-problem choice picked slices
+    def run_slow(pw, pc, cpl):
+        infos, wall = run(pw, pc, cpl)
+        return infos, wall * (3.0 if pc and any(c == 2 for c in pc) else 1.0)
+
+    slow = autotune.search(run_slow, ps, 64)
+    assert slow["problem_col_slices"] == [1] * len(ps)
+    assert any(t["problem_workgroups"] == slow["problem_workgroups"]
+               and t["problem_col_slices"] == slow["problem_col_slices"]
+               and t["wall_s"] == slow["wall_s"] for t in slow["trials"])
 
 
 def _fit_joint(lib, opts=None, **kw):
