@@ -88,7 +88,10 @@ typedef struct {
      * shape first (a call with the same options returns it in concord_info). */
     uint64_t *device_timestamps;
     int32_t timestamp_steps;
-    int32_t reserved;
+    /* Row rewrites (W in HBM): 0 = automatic (in the background, on the waves
+     * that hold no rows, during the next step, when such waves exist and the
+     * pending depth is at least 4), 1 = always right after their step. */
+    int32_t sync_rewrites;
     /* Optional device p x p array (element type dt): receives the maintained
      * product W = Omega S as the solve leaves it (for checks). */
     void *w_out;
@@ -177,6 +180,9 @@ typedef struct {
      * columns (c_b must divide the workgroup count, be <= p_b, and leave
      * ceil(p_b / row groups) <= 2 * block_threads).  NULL = one slice each. */
     const int32_t *problem_col_slices;
+    /* 1 = row rewrites right after their step, as concord_options.sync_rewrites */
+    int32_t sync_rewrites;
+    int32_t reserved;
 } concord_batch_options;
 
 /*

@@ -86,7 +86,7 @@ class ConcordOptions(ctypes.Structure):
         ("delta_trace", ctypes.POINTER(ctypes.c_double)),
         ("device_timestamps", ctypes.c_void_p),
         ("timestamp_steps", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("sync_rewrites", ctypes.c_int32),
         ("w_out", ctypes.c_void_p),
         ("active_set", ctypes.c_int32),
         ("active_maxit", ctypes.c_int32),
@@ -101,6 +101,8 @@ class ConcordBatchOptions(ctypes.Structure):
         ("cols_per_lane", ctypes.c_int32),
         ("problem_workgroups", ctypes.POINTER(ctypes.c_int32)),
         ("problem_col_slices", ctypes.POINTER(ctypes.c_int32)),
+        ("sync_rewrites", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -202,7 +204,8 @@ def _raise(code: int, what: str):
 def fit(X: torch.Tensor, lam: float, tol: float = 1e-6, maxit: int = 500, *, kind: str = "S",
         omega0: torch.Tensor | None = None, out: torch.Tensor | None = None, stream=None,
         row_groups: int = 0, col_slices: int = 0, block_threads: int = 0, w_in_lds: int = 0,
-        pending_depth: int = 0, trace: bool = False, check: bool = True,
+        pending_depth: int = 0, sync_rewrites: bool = False, trace: bool = False,
+        check: bool = True,
         timestamps: torch.Tensor | None = None, w_out: torch.Tensor | None = None,
         active_set: bool = False, active_maxit: int = 0):
     """One CONCORD-PCD solve.  X is S (p x p) or, with kind='Y', Y (n x p).
@@ -237,7 +240,8 @@ def fit(X: torch.Tensor, lam: float, tol: float = 1e-6, maxit: int = 500, *, kin
         o0 = ctypes.c_void_p(omega0.data_ptr())
     info = ConcordInfo()
     opts = ConcordOptions(row_groups, col_slices, block_threads, w_in_lds, pending_depth, None,
-                          None, 0, 0, None, int(bool(active_set)), int(active_maxit))
+                          None, 0, int(bool(sync_rewrites)), None, int(bool(active_set)),
+                          int(active_maxit))
     if w_out is not None:
         _check_dev(w_out, "w_out")
         if w_out.dtype != X.dtype or tuple(w_out.shape) != (p, p):
@@ -312,7 +316,8 @@ def fit_noalloc(X: torch.Tensor, lam: float, tol: float = 1e-6, maxit: int = 500
 def fit_joint(X1: torch.Tensor, X2: torch.Tensor, lam1: float, lam2: float, tol: float = 1e-6,
               maxit: int = 500, *, kind: str = "S", omega0=(None, None), outs=None,
               stream=None, row_groups: int = 0, col_slices: int = 0, block_threads: int = 0,
-              w_in_lds: int = 0, pending_depth: int = 0, trace: bool = False,
+              w_in_lds: int = 0, pending_depth: int = 0, sync_rewrites: bool = False,
+              trace: bool = False,
               check: bool = True):
     """Joint estimation of two precision matrices with a fused penalty
     (Section 6).  X1, X2 are S_1, S_2 (p x p) or, with kind='Y', Y_1, Y_2
@@ -353,7 +358,7 @@ def fit_joint(X1: torch.Tensor, X2: torch.Tensor, lam1: float, lam2: float, tol:
         o0.append(ctypes.c_void_p(o.data_ptr()))
     info = ConcordJointInfo()
     opts = ConcordOptions(row_groups, col_slices, block_threads, w_in_lds, pending_depth, None,
-                          None, 0, 0, None, 0, 0)
+                          None, 0, int(bool(sync_rewrites)), None, 0, 0)
     tr = None
     if trace:
         tr = (ctypes.c_double * int(maxit))()
@@ -376,7 +381,7 @@ def fit_joint(X1: torch.Tensor, X2: torch.Tensor, lam1: float, lam2: float, tol:
 def fit_batched(Xs, lambdas, tol: float = 1e-6, maxit: int = 500, *, kind: str = "S",
                 outs=None, stream=None, workgroups: int = 0, block_threads: int = 0,
                 pending_depth: int = 0, problem_workgroups=None, problem_col_slices=None,
-                cols_per_lane: int = 0, check: bool = True):
+                cols_per_lane: int = 0, sync_rewrites: bool = False, check: bool = True):
     """B independent solves along lambda paths in one persistent launch.
 
     Xs: list of B device tensors (S_b, or Y_b with kind='Y'), one dtype.
@@ -436,7 +441,7 @@ def fit_batched(Xs, lambdas, tol: float = 1e-6, maxit: int = 500, *, kind: str =
     oa = (vp * (B * L))(*[outs[b][l].data_ptr() for b in range(B) for l in range(L)])
     infos = (ConcordInfo * (B * L))()
     opts = ConcordBatchOptions(workgroups, block_threads, pending_depth, cols_per_lane, None,
-                               None)
+                               None, int(bool(sync_rewrites)), 0)
     pw = pc = None
     if problem_workgroups is not None:
         if len(problem_workgroups) != B:
@@ -461,7 +466,8 @@ def fit_batched(Xs, lambdas, tol: float = 1e-6, maxit: int = 500, *, kind: str =
 def backward(S: torch.Tensor, omega: torch.Tensor, grad_omega: torch.Tensor, tol: float = 1e-10,
              maxit: int = 2000, *, out: torch.Tensor | None = None, stream=None,
              row_groups: int = 0, col_slices: int = 0, block_threads: int = 0,
-             w_in_lds: int = 0, pending_depth: int = 0, check: bool = True):
+             w_in_lds: int = 0, pending_depth: int = 0, sync_rewrites: bool = False,
+             check: bool = True):
     """Implicit gradient of Omega-hat = fit(S, lam): returns (dL/dS, dL/dlam, info)
     for dL/dOmega-hat = grad_omega.  dL/dS is the symmetric gradient."""
     lib = load()
@@ -478,7 +484,7 @@ def backward(S: torch.Tensor, omega: torch.Tensor, grad_omega: torch.Tensor, tol
     info = ConcordInfo()
     gl = ctypes.c_double(0.0)
     opts = ConcordOptions(row_groups, col_slices, block_threads, w_in_lds, pending_depth, None,
-                          None, 0, 0, None)
+                          None, 0, int(bool(sync_rewrites)), None)
     with torch.cuda.device(S.device):
         code = lib.concord_backward_ex(ctypes.c_void_p(S.data_ptr()),
                                        ctypes.c_void_p(omega.data_ptr()), p,

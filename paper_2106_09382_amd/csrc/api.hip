@@ -365,6 +365,9 @@ int fit_impl(concord_input kind, const void *X, int64_t n64, int64_t p64, double
     P.nc_max = sh.nc_max;
     P.depth = sh.depth;
     P.rpt = sh.rpt;
+    set_overlap(P, sh.threads, (size_t)max_shared_per_block());
+    if (opts && opts->sync_rewrites)
+        P.ovl = 0;
     P.lam = (T)lambda;
     P.tol = (T)tol;
     P.tol_coef = (sizeof(T) == 4) ? T(16.0 * 1.1920928955078125e-07) : T(0);  // 16 eps_f32
@@ -660,6 +663,9 @@ int backward_impl(const void *Sv, const void *omv, int64_t p64, const void *Cv, 
     P.nc_max = sh.nc_max;
     P.depth = sh.depth;
     P.rpt = sh.rpt;
+    set_overlap(P, sh.threads, (size_t)max_shared_per_block());
+    if (opts && opts->sync_rewrites)
+        P.ovl = 0;
     P.tol = (T)tol;
     P.tol_coef = (sizeof(T) == 4) ? T(16.0 * 1.1920928955078125e-07) : T(0);
     P.spin_limit = kSpinLimit;
@@ -795,7 +801,7 @@ int batched_chunk(int B0, int B1, concord_input kind, const void *const *X, cons
                   const int64_t *pv, int L, const double *lambdas, double tol, int maxit,
                   void *const *omega, concord_info *info, hipStream_t stream,
                   const std::vector<int> &Gb, const std::vector<int> &Cb, int threads, int depth,
-                  int cpl)
+                  int cpl, bool sync_rw)
 {
     const int NB = B1 - B0;
     hipEvent_t ev[4] = {};
@@ -814,7 +820,7 @@ int batched_chunk(int B0, int B1, concord_input kind, const void *const *X, cons
     // Per-problem shapes and workspace offsets.
     // Problem q: G = Gr x Gc workgroups (row groups x column slices).
     struct Prob {
-        int p, G, Gr, Gc, nr, nc, m;
+        int p, G, Gr, Gc, nr, nc, m, ovl;
         size_t oS, oW, oOmp, oOmdp, oSd, oPc, oPd, oFlags, oRed, oOut, oRec, oLam, oOm;
     };
     std::vector<Prob> pr(NB);
@@ -853,6 +859,10 @@ int batched_chunk(int B0, int B1, concord_input kind, const void *const *X, cons
         probe.nr_max = P.nr;
         probe.nc_max = P.nc;
         probe.depth = depth;
+        set_overlap(probe, threads, (size_t)max_shared_per_block());
+        if (sync_rw)
+            probe.ovl = 0;
+        P.ovl = probe.ovl;
         lds = std::max(lds, sweep_lds_bytes<T>(probe));
         Gtot += P.G;
     }
@@ -922,6 +932,7 @@ int batched_chunk(int B0, int B1, concord_input kind, const void *const *X, cons
         D.nc_max = P.nc;
         D.depth = depth;
         D.rpt = 2;
+        D.ovl = P.ovl;
         D.lam = (T)hl[(size_t)q * L];
         D.tol = (T)tol;
         D.tol_coef = (sizeof(T) == 4) ? T(16.0 * 1.1920928955078125e-07) : T(0);
@@ -1112,7 +1123,8 @@ int batched_impl(int B, concord_input kind, const void *const *X, const int64_t 
         for (int b = b0; b < b1; ++b)
             Gb[b] = G[b - b0];
         const int rc = batched_chunk<T>(b0, b1, kind, X, n, pv, L, lambdas, tol, maxit, omega,
-                                        info, stream, Gb, Cb, threads, depth, cpl);
+                                        info, stream, Gb, Cb, threads, depth, cpl,
+                                        o && o->sync_rewrites);
         worst = merge_status(worst, rc);
         if (rc == CONCORD_ENOMEM || rc == CONCORD_EDEVICE || rc == CONCORD_ELAUNCH)
             return rc;
@@ -1246,6 +1258,9 @@ int joint_impl(concord_input kind, const void *const X[2], const int64_t n[2], i
         Q.nc_max = sh.nc_max;
         Q.depth = sh.depth;
         Q.rpt = sh.rpt;
+        set_overlap(Q, sh.threads, (size_t)max_shared_per_block());
+        if (opts && opts->sync_rewrites)
+            Q.ovl = 0;
         Q.lam = (T)lam1;
         Q.tol = (T)tol;
         Q.tol_coef = (sizeof(T) == 4) ? T(16.0 * 1.1920928955078125e-07) : T(0);

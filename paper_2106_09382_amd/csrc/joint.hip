@@ -19,14 +19,15 @@
 
 namespace concord {
 
-template <typename T, bool WLDS, int RPT>
+// BG: row rewrites right after each step (0) or in the background (1).
+template <typename T, bool WLDS, int RPT, int BG>
 __global__ void __launch_bounds__(512) pcd_joint_kernel(SweepParams<T> P0, SweepParams<T> P1)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int G = (int)gridDim.x / 2;
     const int pop = (int)blockIdx.x >= G ? 1 : 0;
-    pcd_solve<T, WLDS, RPT, 2, false, false, true>(pop ? P1 : P0, (int)blockIdx.x - pop * G, G,
-                                                   smem_raw);
+    pcd_solve<T, WLDS, RPT, 2, false, false, true, BG>(pop ? P1 : P0, (int)blockIdx.x - pop * G,
+                                                       G, smem_raw);
 }
 
 template <typename T>
@@ -34,7 +35,8 @@ hipError_t launch_sweep_joint(const SweepParams<T> &P0, const SweepParams<T> &P1
                               hipStream_t stream)
 {
     if (P0.Gr != P1.Gr || P0.Gc != P1.Gc || P0.nr_max != P1.nr_max || P0.depth != P1.depth ||
-        P0.w_lds != P1.w_lds || P0.rpt != P1.rpt || P0.p != P1.p || P0.pop != 0 || P1.pop != 1)
+        P0.w_lds != P1.w_lds || P0.rpt != P1.rpt || P0.p != P1.p || P0.pop != 0 || P1.pop != 1 ||
+        P0.ovl != P1.ovl || (P0.ovl && P0.w_lds))
         return hipErrorInvalidValue;
     const size_t lds = sweep_lds_bytes(P0);
     const int G = P0.Gr * P0.Gc;
@@ -42,11 +44,14 @@ hipError_t launch_sweep_joint(const SweepParams<T> &P0, const SweepParams<T> &P1
     void *args[] = {&a0, &a1};
     const void *fn;
     if (P0.w_lds)
-        fn = P0.rpt <= 1 ? (const void *)pcd_joint_kernel<T, true, 1>
-                         : (const void *)pcd_joint_kernel<T, true, 2>;
+        fn = P0.rpt <= 1 ? (const void *)pcd_joint_kernel<T, true, 1, 0>
+                         : (const void *)pcd_joint_kernel<T, true, 2, 0>;
+    else if (P0.ovl)
+        fn = P0.rpt <= 1 ? (const void *)pcd_joint_kernel<T, false, 1, 1>
+                         : (const void *)pcd_joint_kernel<T, false, 2, 1>;
     else
-        fn = P0.rpt <= 1 ? (const void *)pcd_joint_kernel<T, false, 1>
-                         : (const void *)pcd_joint_kernel<T, false, 2>;
+        fn = P0.rpt <= 1 ? (const void *)pcd_joint_kernel<T, false, 1, 0>
+                         : (const void *)pcd_joint_kernel<T, false, 2, 0>;
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess)
         return e;

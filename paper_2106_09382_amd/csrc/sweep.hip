@@ -7,20 +7,23 @@ namespace concord {
 template <typename T>
 size_t sweep_lds_bytes(const SweepParams<T> &P)
 {
-    size_t bytes = sizeof(T) * ((size_t)P.nr_max * P.depth + 16);
+    const size_t nb = P.ovl ? 2 : 1;  // sets of pending lists
+    size_t bytes = sizeof(T) * (nb * P.nr_max * P.depth + 16);
     if (P.w_lds)
         bytes += sizeof(T) * (size_t)P.nr_max * P.nc_max;
-    bytes += sizeof(int) * ((size_t)P.nr_max * P.depth + 2 * (size_t)P.nr_max + 8);
+    bytes += sizeof(int) * (nb * P.nr_max * P.depth + nb * P.nr_max + 2 * (size_t)P.nr_max + 8);
     bytes += sizeof(unsigned) * 16;
     bytes += 8 + sizeof(double) * 16 + sizeof(unsigned long long) * 16;  // path summaries
     return bytes;
 }
 
-template <typename T, bool WLDS, int RPT, bool ADJ, bool TAB>
+// BG: row rewrites right after each step (0) or in the background (1); the
+// host picks the instantiation from P.ovl.
+template <typename T, bool WLDS, int RPT, bool ADJ, bool TAB, int BG>
 __global__ void __launch_bounds__(512) pcd_sweep_kernel(SweepParams<T> P)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    pcd_solve<T, WLDS, RPT, 2, ADJ, TAB, false>(P, blockIdx.x, gridDim.x, smem_raw);
+    pcd_solve<T, WLDS, RPT, 2, ADJ, TAB, false, BG>(P, blockIdx.x, gridDim.x, smem_raw);
 }
 
 // Many independent problems in one launch: workgroup blockIdx.x serves
@@ -39,19 +42,25 @@ __global__ void __launch_bounds__(512)
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const SweepParams<T> P = descs[wg_problem[blockIdx.x]];
     const int g = (int)blockIdx.x - P.g0, G = P.Gr * P.Gc;
-    pcd_solve<T, false, 2, CPL, false, false, false>(P, g, G, smem_raw);
+    pcd_solve<T, false, 2, CPL, false, false, false, 2>(P, g, G, smem_raw);
 }
 
 namespace {
 
 // The schedule is a template argument: Algorithm 1's round robin computes
 // partners in registers, a colouring table (forward solves only) loads them.
+// Background rewrites exist only with W in HBM.
 template <typename T, bool WLDS, bool ADJ, bool TAB>
-const void *pick_kernel(int rpt)
+const void *pick_kernel(int rpt, int ovl)
 {
+    if constexpr (!WLDS) {
+        if (ovl)
+            return rpt <= 1 ? (const void *)pcd_sweep_kernel<T, false, 1, ADJ, TAB, 1>
+                            : (const void *)pcd_sweep_kernel<T, false, 2, ADJ, TAB, 1>;
+    }
     if (rpt <= 1)
-        return (const void *)pcd_sweep_kernel<T, WLDS, 1, ADJ, TAB>;
-    return (const void *)pcd_sweep_kernel<T, WLDS, 2, ADJ, TAB>;
+        return (const void *)pcd_sweep_kernel<T, WLDS, 1, ADJ, TAB, 0>;
+    return (const void *)pcd_sweep_kernel<T, WLDS, 2, ADJ, TAB, 0>;
 }
 
 }  // namespace
@@ -67,14 +76,14 @@ hipError_t launch_sweep(const SweepParams<T> &P, int threads, hipStream_t stream
     if (P.adj_g && P.part)
         return hipErrorInvalidValue;
     if (P.adj_g)
-        fn = P.w_lds ? pick_kernel<T, true, true, false>(P.rpt)
-                     : pick_kernel<T, false, true, false>(P.rpt);
+        fn = P.w_lds ? pick_kernel<T, true, true, false>(P.rpt, 0)
+                     : pick_kernel<T, false, true, false>(P.rpt, P.ovl);
     else if (P.part)
-        fn = P.w_lds ? pick_kernel<T, true, false, true>(P.rpt)
-                     : pick_kernel<T, false, false, true>(P.rpt);
+        fn = P.w_lds ? pick_kernel<T, true, false, true>(P.rpt, 0)
+                     : pick_kernel<T, false, false, true>(P.rpt, P.ovl);
     else
-        fn = P.w_lds ? pick_kernel<T, true, false, false>(P.rpt)
-                     : pick_kernel<T, false, false, false>(P.rpt);
+        fn = P.w_lds ? pick_kernel<T, true, false, false>(P.rpt, 0)
+                     : pick_kernel<T, false, false, false>(P.rpt, P.ovl);
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess)
         return e;

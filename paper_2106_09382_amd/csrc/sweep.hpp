@@ -59,6 +59,8 @@ struct SweepParams {
     int nc_max;        // max columns per workgroup
     int depth;         // pending row updates held before a row is flushed (>= 2)
     int rpt;           // rows per thread (1, 2 or 4)
+    int ovl;           // row rewrites run on the waves without rows, during the next
+                       // step, from a second set of pending lists (set_overlap)
     T lam;
     T tol;
     T tol_coef;        // tol_eff = max(tol, tol_coef * max_i omega_ii)
@@ -121,6 +123,24 @@ struct Sentinel<float> {
 
 template <typename T>
 size_t sweep_lds_bytes(const SweepParams<T> &P);
+
+// Background row rewrites (P.ovl) need W in HBM, a wave that holds no rows
+// (rows are dealt to threads in order, so waves past ceil(nr_max / 64) hold
+// none), room in LDS for the second set of pending lists, and lists of at
+// least 4 entries.  A row takes at most two updates per step (its pair and,
+// after the last colour, its diagonal), so with depth >= 4 a row that went
+// on in its other set is not listed again in the very next step, while the
+// background rewrite of its first set is still running.
+template <typename T>
+inline void set_overlap(SweepParams<T> &P, int threads, size_t lds_cap)
+{
+    P.ovl = 0;
+    if (P.w_lds || P.depth < 4 || (P.nr_max + 63) / 64 >= threads / 64)
+        return;
+    P.ovl = 1;
+    if (sweep_lds_bytes(P) > lds_cap)
+        P.ovl = 0;
+}
 
 template <typename T>
 hipError_t launch_sweep(const SweepParams<T> &P, int threads, hipStream_t stream);

@@ -189,29 +189,36 @@ __device__ __forceinline__ void joint_diag(T s1, T c1, T s2, T c2, T lam2, T &y1
 
 // Rewrites the segments of the listed rows with their pending updates:
 // W_ic <- fma(d_e, S_{src_e, c}, ...) in list order, for c in the slice.
-// Work is cut into (row, 64 * CPL column chunk) units dealt out to the waves;
-// each lane handles CPL columns 64 apart (every load is one coalesced row
-// segment), so CPL * (n + 1) loads are in flight per lane.
+// An entry 2 k + s names row k and its set s of pending lists (the lists of
+// set s start at pj + s * LB, pdl + s * LB and np + s * NR).  Work is cut into
+// (row, 64 * CPL column chunk) units dealt out to waves wv0 and up; each lane
+// handles CPL columns 64 apart (every load is one coalesced row segment), so
+// CPL * (n + 1) loads are in flight per lane.
 template <typename T, bool WLDS, int CPL>
 __device__ void flush_rows(const int *rows, int nrows, const int *pj, const T *pdl,
-                           const int *np, int D, int a, int Gr, int p, int c0, int nc,
-                           const T *__restrict__ S, T *__restrict__ Wg, T *wblk)
+                           const int *np, int LB, int NR, int D, int a, int Gr, int p, int c0,
+                           int nc, const T *__restrict__ S, T *__restrict__ Wg, T *wblk,
+                           int wv0 = 0)
 {
     constexpr int CW = 64 * CPL;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int lane = threadIdx.x & 63, wv = (threadIdx.x >> 6) - wv0;
+    const int nw = (blockDim.x >> 6) - wv0;
     const int chunks = (nc + CW - 1) / CW;
     const int units = nrows * chunks;
     for (int u = wv; u < units; u += nw) {
         const int fr = u / chunks, ch = u - fr * chunks;
-        const int k = rows[fr];
+        const int ks = rows[fr];
+        const int k = ks >> 1, set = ks & 1;
         const int i = a + k * Gr;
-        const int n = np[k];
+        const int n = np[set * NR + k];
+        const int *pjs = pj + (size_t)set * LB + (size_t)k * D;
+        const T *pdls = pdl + (size_t)set * LB + (size_t)k * D;
         const int cl = ch * CW + lane;
         T sv[kMaxDepth][CPL];
 #pragma unroll
         for (int e = 0; e < kMaxDepth; ++e) {
             if (e < n) {
-                const T *row = S + (size_t)pj[k * D + e] * p + c0;
+                const T *row = S + (size_t)pjs[e] * p + c0;
 #pragma unroll
                 for (int q = 0; q < CPL; ++q)
                     sv[e][q] = (cl + 64 * q < nc) ? row[cl + 64 * q] : T(0);
@@ -225,7 +232,7 @@ __device__ void flush_rows(const int *rows, int nrows, const int *pj, const T *p
 #pragma unroll
         for (int e = 0; e < kMaxDepth; ++e) {
             if (e < n) {
-                const T d = pdl[k * D + e];
+                const T d = pdls[e];
 #pragma unroll
                 for (int q = 0; q < CPL; ++q)
                     v[q] = fma(d, sv[e][q], v[q]);
@@ -264,20 +271,27 @@ template <typename T, bool JNT>
 struct RowNext : RowJoint<T, JNT> {
     int j;        // partner in the step (-1: idle)
     int kn;       // column published by the step (-1: none in this slice)
-    int n;        // pending entries the published value folds in
+    int n;        // pending entries the published values fold in ...
+    int set;      // ... taken from this set of pending lists
     bool last;    // the step is the last colour (diagonal step follows)
     bool pubd;    // the step publishes W_ii for the following last colour
-    T w, od, s_ji, wb, s_jn, s_in;
+    T w, od, s_ji, s_jn, s_in;
+    T wb;         // stored W_{i,kn}
+    T wd;         // stored W_ii, when the step publishes it
     T sd_lo, sd_hi;  // S_ll and S_hh of the pair (l < h), whose sum is eq. (3)'s denominator
     T sii;        // S_ii, for the diagonal step after the last colour
     T g;          // adjoint mode: right-hand side of the pair (NaN: pair not free)
     T sv[kMaxDepth];
 };
 
+// `pj` is the start of the set of pending lists `set`, whose first n entries
+// of row k the step's published values fold in.  With loadw false the stored
+// W entries are not read here (a rewrite of the row may be running): the step
+// reads them itself, after the barrier that ends the rewrite.
 template <typename T, bool WLDS, bool TAB, bool JNT>
 __device__ __forceinline__ void load_next(RowNext<T, JNT> &x, const Circle &C, const int *part, int mt,
-                                          int r1, int i, int k,
-                                          int n, const int *pj, int D, int NR, int p, int c0,
+                                          int r1, int i, int k, int n, int set, bool loadw,
+                                          const int *pj, int D, int NR, int p, int c0,
                                           int c1, int nc, const T *__restrict__ S,
                                           const T *__restrict__ Wg, const T *wblk,
                                           const T *__restrict__ omp, const T *__restrict__ omdp,
@@ -300,6 +314,7 @@ __device__ __forceinline__ void load_next(RowNext<T, JNT> &x, const Circle &C, c
     x.last = (r1 == m - 1);
     x.pubd = (rn1 == m - 1) && i >= c0 && i < c1;
     x.n = n;
+    x.set = set;
     x.w = (x.j >= 0) ? omp[(size_t)r1 * NR + k] : T(0);
     x.g = (adjg && x.j >= 0) ? adjg[(size_t)r1 * NR + k] : T(0);
     x.od = x.last ? omdp[k] : T(0);
@@ -318,8 +333,11 @@ __device__ __forceinline__ void load_next(RowNext<T, JNT> &x, const Circle &C, c
         x.sdo_hi = (x.j >= 0) ? sdo[hi] : T(0);
         x.sio = x.last ? sdo[i] : T(0);
     }
+    x.wd = (x.pubd && loadw) ? (WLDS ? wblk[(size_t)k * nc + (i - c0)] : Wg[(size_t)i * p + i])
+                             : T(0);
     if (x.kn >= 0) {
-        x.wb = WLDS ? wblk[(size_t)k * nc + (x.kn - c0)] : Wg[(size_t)i * p + x.kn];
+        x.wb = loadw ? (WLDS ? wblk[(size_t)k * nc + (x.kn - c0)] : Wg[(size_t)i * p + x.kn])
+                     : T(0);
 #pragma unroll
         for (int e = 0; e < kMaxDepth; ++e)
             if (e < n)
@@ -330,20 +348,25 @@ __device__ __forceinline__ void load_next(RowNext<T, JNT> &x, const Circle &C, c
 }
 
 
-// End of one lambda of a path: apply every pending row update to the stored
-// W block, then write this workgroup's block of the dense Omega (rows
-// i = a (mod Gr), columns of slice b) and add its share of |E-hat| and of the
-// objective F(Omega) = -sum log omega_ii + 1/2 sum_ij omega_ij W_ij
-// + lam sum_{i<j} |omega_ij| to the lambda's record.
+// Applies every pending row update to the stored W block, in list order:
+// first the rewrite still owed for the last step's rows (when rewrites run
+// in the background, `owed` lists nf_owed of them), then each row's current
+// set of lists.  `spare` is an flist half that no rewrite is reading.
+// Afterwards every list is empty.
 template <typename T, bool WLDS, int RPT, int CPL>
-__device__ void end_of_lambda(const SweepParams<T> &P, int l, T lam, const Circle &C, int a,
-                              int Gr, int nr, int NR, int D, int c0, int nc, int *np, int *flist,
-                              int *ncount, const int *pj, const T *pdl, bool (&flushed)[RPT],
-                              T *wblk, const T *omp, const T *omdp, double *dred,
-                              unsigned long long *nred)
+__device__ void flush_all(const SweepParams<T> &P, int a, int Gr, int nr, int NR, int D, int c0,
+                          int nc, int *np, const int *pj, const T *pdl, const int *owed,
+                          int &nf_owed, int *spare, int *ncount, const int (&cset)[RPT],
+                          bool (&flushed)[RPT], T *wblk)
 {
-    const int tid = threadIdx.x, nthr = blockDim.x, p = P.p;
+    const int tid = threadIdx.x, nthr = blockDim.x, p = P.p, LB = NR * D;
     __syncthreads();
+    if (nf_owed > 0) {
+        flush_rows<T, WLDS, CPL>(owed, nf_owed, pj, pdl, np, LB, NR, D, a, Gr, p, c0, nc, P.S,
+                                 P.W, wblk);
+        nf_owed = 0;
+        __syncthreads();
+    }
     if (tid == 0)
         *ncount = 0;
     __syncthreads();
@@ -351,23 +374,38 @@ __device__ void end_of_lambda(const SweepParams<T> &P, int l, T lam, const Circl
     for (int u = 0; u < RPT; ++u) {
         const int k = tid + u * nthr;
         if (k < nr) {
-            if (flushed[u]) {
+            if (flushed[u]) {  // rewritten after the last step (one set of lists)
                 np[k] = 0;
                 flushed[u] = false;
             }
-            if (np[k] > 0)
-                flist[atomicAdd(ncount, 1)] = k;
+            if (np[cset[u] * NR + k] > 0)
+                spare[atomicAdd(ncount, 1)] = 2 * k + cset[u];
         }
     }
     __syncthreads();
-    flush_rows<T, WLDS, CPL>(flist, *ncount, pj, pdl, np, D, a, Gr, p, c0, nc, P.S, P.W, wblk);
+    flush_rows<T, WLDS, CPL>(spare, *ncount, pj, pdl, np, LB, NR, D, a, Gr, p, c0, nc, P.S, P.W,
+                             wblk);
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < RPT; ++u) {
         const int k = tid + u * nthr;
         if (k < nr)
-            np[k] = 0;
+            np[cset[u] * NR + k] = 0;
     }
+}
+
+// End of one lambda of a path: apply every pending row update to the stored
+// W block (the caller has done so with flush_all), then write this
+// workgroup's block of the dense Omega (rows i = a (mod Gr), columns of
+// slice b) and add its share of |E-hat| and of the objective
+// F(Omega) = -sum log omega_ii + 1/2 sum_ij omega_ij W_ij
+// + lam sum_{i<j} |omega_ij| to the lambda's record.
+template <typename T, bool WLDS, int RPT, int CPL>
+__device__ void end_of_lambda(const SweepParams<T> &P, int l, T lam, const Circle &C, int a,
+                              int Gr, int nr, int NR, int c0, int nc, T *wblk, const T *omp,
+                              const T *omdp, double *dred, unsigned long long *nred)
+{
+    const int tid = threadIdx.x, nthr = blockDim.x, p = P.p;
     T *om = P.omega_out[l];
     double part = 0.0;
     unsigned long long cnt = 0;
@@ -436,7 +474,10 @@ __device__ void end_of_lambda(const SweepParams<T> &P, int l, T lam, const Circl
 // two-population solve (Section 6): each pair and diagonal entry is updated by
 // the block minimisers joint_pair / joint_diag from both populations' published
 // entries, and this workgroup also keeps its copy of the other omega.
-template <typename T, bool WLDS, int RPT, int CPL, bool ADJ, bool TAB, bool JNT>
+// BG selects the rewrite mode: 0 = right after each step, 1 = in the
+// background (the host has set P.ovl), 2 = as P.ovl says (one kernel for
+// problems of both kinds, e.g. a batch).
+template <typename T, bool WLDS, int RPT, int CPL, bool ADJ, bool TAB, bool JNT, int BG>
 __device__ void pcd_solve(const SweepParams<T> &P, int g, int G, unsigned char *smem_raw)
 {
     static_assert(!(JNT && (ADJ || TAB)), "joint mode runs Algorithm 1's forward sweeps only");
@@ -455,14 +496,19 @@ __device__ void pcd_solve(const SweepParams<T> &P, int g, int G, unsigned char *
     const int NR = P.nr_max, D = P.depth;
     const int PS = Gr * NR;  // published slots per colour; row i sits at (i mod Gr) * NR + i / Gr
 
-    // LDS carve-up (sizes fixed by the host in sweep_lds_bytes).
-    T *pdl = reinterpret_cast<T *>(smem_raw);   // pending changes, NR x D
-    T *wred = pdl + (size_t)NR * D;             // 16 wave partials
+    // LDS carve-up (sizes fixed by the host in sweep_lds_bytes).  The pending
+    // lists come in NB sets: with background rewrites a row whose lists are
+    // being rewritten keeps appending to its other set.
+    const bool ovl = (BG == 2) ? (P.ovl != 0) : (BG == 1);
+    const int NB = ovl ? 2 : 1;
+    const int LB = NR * D;                      // one set of lists
+    T *pdl = reinterpret_cast<T *>(smem_raw);   // pending changes, NB x NR x D
+    T *wred = pdl + (size_t)NB * LB;            // 16 wave partials
     T *wblk = wred + 16;                        // W block (LDS variant): NR x nc_max
-    int *pj = reinterpret_cast<int *>(wblk + (WLDS ? (size_t)NR * P.nc_max : 0));  // NR x D sources
-    int *np = pj + (size_t)NR * D;              // pending count per row
-    int *flist = np + NR;                       // rows to rewrite this step
-    int *nflush = flist + NR;                   // [3] counters, by step mod 3; [3] spare
+    int *pj = reinterpret_cast<int *>(wblk + (WLDS ? (size_t)NR * P.nc_max : 0));  // NB x NR x D sources
+    int *np = pj + (size_t)NB * LB;             // pending count per row and set, NB x NR
+    int *flist = np + NB * NR;                  // rows to rewrite, 2 k + set, two halves by step parity
+    int *nflush = flist + 2 * NR;               // [3] counters, by step mod 3; [3] spare
     int *s_fail = nflush + 4;
     int *sfail3 = s_fail + 1;                   // [3] a wait of the step failed, by step mod 3
     unsigned *ured = reinterpret_cast<unsigned *>(sfail3 + 3);  // 16 wave partials
@@ -480,7 +526,7 @@ __device__ void pcd_solve(const SweepParams<T> &P, int g, int G, unsigned char *
     T *__restrict__ omdp_o = JNT ? P.jo_omdp + (size_t)g * NR : nullptr;
     const T lam2 = JNT ? P.lam2 : T(0);
 
-    for (int k = tid; k < NR; k += nthr)
+    for (int k = tid; k < NB * NR; k += nthr)
         np[k] = 0;
     if (tid == 0) {
         nflush[0] = 0;
@@ -503,17 +549,28 @@ __device__ void pcd_solve(const SweepParams<T> &P, int g, int G, unsigned char *
     T dloc = T(0), gloc = T(0);
     unsigned moved = 0, moved_d = 0;  // pairs / diagonals that changed (counted once each)
     int t = 0, converged = 0, failed = 0;
-    bool flushed[RPT];
+    // Per row: the set of lists it appends to; with one set, whether its list
+    // was rewritten after the last step (it restarts at the next step); with
+    // two, whether its other set is being rewritten during this step, and
+    // whether the step must read its stored W entries itself.
+    int cset[RPT];
+    bool flushed[RPT], inflight[RPT], reload[RPT];
     RowNext<T, JNT> nx[RPT];
 #pragma unroll
     for (int u = 0; u < RPT; ++u) {
-        flushed[u] = false;
+        cset[u] = 0;
+        flushed[u] = inflight[u] = reload[u] = false;
         const int k = tid + u * nthr;
         if (k < nr)
-            load_next<T, WLDS, TAB, JNT>(nx[u], C, P.part, m, 0, a + k * Gr, k, 0, pj, D, NR, p,
-                                         c0, c1, nc, S, Wg, wblk, omp, omdp, adjg, omp_o, omdp_o,
-                                         P.jo_S, sd, P.jo_sd);
+            load_next<T, WLDS, TAB, JNT>(nx[u], C, P.part, m, 0, a + k * Gr, k, 0, 0, true, pj, D,
+                                         NR, p, c0, c1, nc, S, Wg, wblk, omp, omdp, adjg, omp_o,
+                                         omdp_o, P.jo_S, sd, P.jo_sd);
     }
+    // Background rewrites: the waves from fw0 on hold no rows; during each
+    // step they rewrite the rows the previous step listed (nf_owed of them).
+    const int fw0 = (nr + 63) >> 6;
+    const bool bg_wave = ovl && (tid >> 6) >= fw0;
+    int nf_owed = 0;
     // adjoint mode: the diagonal right-hand side and denominator of each row
     T adj_gd[RPT], adj_hd[RPT];
 #pragma unroll
@@ -580,14 +637,34 @@ __device__ void pcd_solve(const SweepParams<T> &P, int g, int G, unsigned char *
             if (ts)
                 ts[0] = __builtin_amdgcn_s_memrealtime();
 
+            // ---- background rewrites: the waves without rows rewrite the rows
+            // the previous step listed while the row waves run this step.  Those
+            // rows append to their other set of lists meanwhile, and read their
+            // stored W entries only after the barrier that ends this step.
+            if (bg_wave && nf_owed > 0)
+                flush_rows<T, WLDS, CPL>(flist + ((step - 1u) & 1u) * NR, nf_owed, pj, pdl, np, LB,
+                                         NR, D, a, Gr, p, c0, nc, S, Wg, wblk, fw0);
+
 #pragma unroll
             for (int u = 0; u < RPT; ++u) {
                 const int k = tid + u * nthr;
                 if (k >= nr || lfail)
                     continue;
                 const int i = a + k * Gr;
-                const RowNext<T, JNT> &x = nx[u];
+                RowNext<T, JNT> &x = nx[u];
                 const int j = x.j;
+
+                // ---- stored W entries that the previous step could not read: a
+                // background rewrite of this row was running then (or the lambda
+                // ended and every row was rewritten).  Issued before the poll, so
+                // that both round trips overlap.
+                if (reload[u]) {
+                    if (x.kn >= 0)
+                        x.wb = WLDS ? wblk[(size_t)k * nc + (x.kn - c0)] : Wg[(size_t)i * p + x.kn];
+                    if (x.pubd)
+                        x.wd = WLDS ? wblk[(size_t)k * nc + (i - c0)] : Wg[(size_t)i * p + i];
+                    reload[u] = false;
+                }
 
                 // ---- poll the published numerator entries of this colour.  The
                 // first poll is issued before anything waits for the operands
@@ -631,13 +708,14 @@ __device__ void pcd_solve(const SweepParams<T> &P, int g, int G, unsigned char *
                 issue_poll();
 
                 // ---- stored entries plus pending updates, for what this step publishes
+                const T *pdlx = pdl + (size_t)x.set * LB + (size_t)k * D;
                 T vpre = T(0), vdpre = T(0);
                 if (x.kn >= 0) {
                     vpre = x.wb;
 #pragma unroll
                     for (int e = 0; e < kMaxDepth; ++e)
                         if (e < x.n)
-                            vpre = fma(pdl[k * D + e], x.sv[e], vpre);
+                            vpre = fma(pdlx[e], x.sv[e], vpre);
                 }
                 // ---- wait for the polled entries, polling again until they are there
                 {
@@ -660,19 +738,23 @@ __device__ void pcd_solve(const SweepParams<T> &P, int g, int G, unsigned char *
                     continue;
                 }
 
-                // ---- a row rewritten last step starts a new pending list.  The
-                // once-per-sweep W_ii read comes after the wait: a load issued
-                // before the poll would hold up the poll's first answer (a
-                // wave's loads complete in order).
+                // ---- with one set of lists, a row rewritten after the last step
+                // starts a new list (its entries are still read by the folds of
+                // this step, which take the list as it was).  The
+                // once-per-sweep gathers of the W_ii fold come after the wait:
+                // loads issued before the poll would hold up the poll's first
+                // answer (a wave's loads complete in order).
                 if (flushed[u]) {
                     np[k] = 0;
                     flushed[u] = false;
                 }
-                const int n0 = np[k];
+                const int cs = cset[u];
+                const int n0 = np[cs * NR + k];
                 if (x.pubd) {
-                    vdpre = WLDS ? wblk[(size_t)k * nc + (i - c0)] : Wg[(size_t)i * p + i];
-                    for (int e = 0; e < n0; ++e)
-                        vdpre = fma(pdl[k * D + e], S[(size_t)pj[k * D + e] * p + i], vdpre);
+                    const int *pjx = pj + (size_t)x.set * LB + (size_t)k * D;
+                    vdpre = x.wd;
+                    for (int e = 0; e < x.n; ++e)
+                        vdpre = fma(pdlx[e], S[(size_t)pjx[e] * p + i], vdpre);
                     // every load of this once-per-sweep fold is consumed; said
                     // explicitly so that the compiler's wait analysis does not
                     // carry them into the next step, whose first register
@@ -749,18 +831,20 @@ __device__ void pcd_solve(const SweepParams<T> &P, int g, int G, unsigned char *
                 }
 
                 // ---- record the changes as pending updates of row i
+                int *pjc = pj + (size_t)cs * LB + (size_t)k * D;
+                T *pdlc = pdl + (size_t)cs * LB + (size_t)k * D;
                 int n = n0;
                 if (del != T(0)) {
-                    pj[k * D + n] = j;
-                    pdl[k * D + n] = del;
+                    pjc[n] = j;
+                    pdlc[n] = del;
                     ++n;
                 }
                 if (dd != T(0)) {
-                    pj[k * D + n] = i;
-                    pdl[k * D + n] = dd;
+                    pjc[n] = i;
+                    pdlc[n] = dd;
                     ++n;
                 }
-                np[k] = n;
+                np[cs * NR + k] = n;
 
                 // ---- publish what the next colour reads from row i
                 if (x.kn >= 0) {
@@ -779,9 +863,9 @@ __device__ void pcd_solve(const SweepParams<T> &P, int g, int G, unsigned char *
                         v = fma(dd, sd[i], v);
                     st_dev(&pdn[a * NR + k], v);
                 }
-                if (n > D - 2) {
-                    flist[atomicAdd(&nflush[s3], 1)] = k;
-                    flushed[u] = true;
+                const bool mark = n > D - 2;
+                if (mark) {
+                    flist[(step & 1u) * NR + atomicAdd(&nflush[s3], 1)] = 2 * k + cs;
                     marked = 1;
                 }
                 T ad = fabs(del) > fabs(dd) ? fabs(del) : fabs(dd);
@@ -795,12 +879,30 @@ __device__ void pcd_solve(const SweepParams<T> &P, int g, int G, unsigned char *
                     moved_d += (dd != T(0)) ? 1u : 0u;
                 }
 
-                // ---- operands of the row's next step.  The stored W entry is
-                // read before this step's rewrites (they start after the
-                // workgroup barrier below), so it is folded with all n entries.
-                load_next<T, WLDS, TAB, JNT>(nx[u], C, P.part, m, rn, i, k, n, pj, D, NR, p, c0,
-                                             c1, nc, S, Wg, wblk, omp, omdp, adjg, omp_o, omdp_o,
-                                             P.jo_S, sd, P.jo_sd);
+                // ---- operands of the row's next step, which folds the n entries
+                // of this list set.  The stored W entries read here are read
+                // before any rewrite of this list (it starts after the barrier
+                // below), so they go with all n entries.  While a background
+                // rewrite of the row's other set runs (listed last step), its W
+                // segment is not read here but at the start of the next step.
+                const bool loadw = !(ovl && inflight[u]);
+                reload[u] = !loadw;
+                inflight[u] = ovl && mark;
+                load_next<T, WLDS, TAB, JNT>(nx[u], C, P.part, m, rn, i, k, n, cs, loadw,
+                                             pj + (size_t)cs * LB, D, NR, p, c0, c1, nc, S, Wg,
+                                             wblk, omp, omdp, adjg, omp_o, omdp_o, P.jo_S, sd,
+                                             P.jo_sd);
+                if (mark) {
+                    if (ovl) {
+                        // the row goes on in its other set of lists, whose
+                        // background rewrite has ended: with depth >= 4 (see
+                        // set_overlap) a row is listed at most every other step
+                        cset[u] = cs ^ 1;
+                        np[(cs ^ 1) * NR + k] = 0;
+                    } else {
+                        flushed[u] = true;  // rewritten right after this step
+                    }
+                }
             }
 
             // ---- every row of the step is done; rewrite the rows whose lists are full.
@@ -823,8 +925,11 @@ __device__ void pcd_solve(const SweepParams<T> &P, int g, int G, unsigned char *
                 failed = 1;
                 break;
             }
-            if (nf > 0) {
-                flush_rows<T, WLDS, CPL>(flist, nf, pj, pdl, np, D, a, Gr, p, c0, nc, S, Wg, wblk);
+            if (ovl) {
+                nf_owed = nf;  // rewritten in the background during the next step
+            } else if (nf > 0) {
+                flush_rows<T, WLDS, CPL>(flist + (step & 1u) * NR, nf, pj, pdl, np, LB, NR, D, a,
+                                         Gr, p, c0, nc, S, Wg, wblk);
                 __syncthreads();
             }
             if (ts)
@@ -868,10 +973,22 @@ __device__ void pcd_solve(const SweepParams<T> &P, int g, int G, unsigned char *
         const bool conv = delta < tol_eff;
         if (conv || tl >= P.maxit) {
             converged = conv ? 1 : 0;
-            if (P.omega_out)
-                end_of_lambda<T, WLDS, RPT, CPL>(P, lidx, lam, C, a, Gr, nr, NR, D, c0, nc, np, flist,
-                                            &nflush[3], pj, pdl, flushed, wblk, omp, omdp, dred,
-                                            nred);
+            if (P.omega_out) {
+                flush_all<T, WLDS, RPT, CPL>(P, a, Gr, nr, NR, D, c0, nc, np, pj, pdl,
+                                             flist + ((step - 1u) & 1u) * NR, nf_owed,
+                                             flist + (step & 1u) * NR, &nflush[3], cset, flushed,
+                                             wblk);
+                end_of_lambda<T, WLDS, RPT, CPL>(P, lidx, lam, C, a, Gr, nr, NR, c0, nc, wblk, omp,
+                                                 omdp, dred, nred);
+                // W now holds every update: the next step reads its stored
+                // entries afresh and folds no list
+#pragma unroll
+                for (int u = 0; u < RPT; ++u) {
+                    reload[u] = true;
+                    inflight[u] = false;
+                    nx[u].n = 0;
+                }
+            }
             if (P.rec && g == 0 && tid == 0) {
                 const unsigned long long now = __builtin_amdgcn_s_memrealtime();
                 P.rec[lidx].t_end = t;
@@ -888,22 +1005,9 @@ __device__ void pcd_solve(const SweepParams<T> &P, int g, int G, unsigned char *
     }
 
     // Apply every pending update so that the stored W is Omega S again.
-    __syncthreads();
-    if (tid == 0)
-        nflush[3] = 0;
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < RPT; ++u) {
-        const int k = tid + u * nthr;
-        if (k < nr) {
-            if (flushed[u])
-                np[k] = 0;
-            if (np[k] > 0)
-                flist[atomicAdd(&nflush[3], 1)] = k;
-        }
-    }
-    __syncthreads();
-    flush_rows<T, WLDS, CPL>(flist, nflush[3], pj, pdl, np, D, a, Gr, p, c0, nc, S, Wg, wblk);
+    flush_all<T, WLDS, RPT, CPL>(P, a, Gr, nr, NR, D, c0, nc, np, pj, pdl,
+                                 flist + ((step - 1u) & 1u) * NR, nf_owed, flist + (step & 1u) * NR,
+                                 &nflush[3], cset, flushed, wblk);
     __syncthreads();
     if (WLDS) {
         for (long e = tid; e < (long)nr * nc; e += nthr) {

@@ -142,6 +142,39 @@ def test_stored_product_is_omega_s(lib, shape, maxit):
     assert np.abs(W - got @ S).max() <= 1e-13 * scale * max(info["sweeps"], 1)
 
 
+# Background row rewrites (the default whenever W is in HBM, some wave holds
+# no rows and the pending depth is at least 4) against rewrites right after
+# each step: the same updates in the same order, so the same bits in Omega and
+# in the stored product W.
+BG_CASES = [
+    (1, dict(w_in_lds=2)),
+    (1, dict(w_in_lds=2, pending_depth=4)),
+    (1, dict(w_in_lds=2, pending_depth=5, block_threads=128)),
+    (2, dict(w_in_lds=2)),
+    (2, dict(w_in_lds=2, row_groups=16, col_slices=4, pending_depth=6)),
+    (2, dict(w_in_lds=2, row_groups=64, col_slices=2, block_threads=256, pending_depth=4)),
+]
+
+
+@pytest.mark.parametrize("config,shape", BG_CASES, ids=[f"{c}-{s}" for c, s in BG_CASES])
+def test_background_rewrites_match_synchronous_bit_for_bit(lib, config, shape):
+    pr = _problem(config)
+    S = pr["S"]
+    lam, tol = (0.3, 1e-8) if config == 1 else (0.2, 1e-7)
+    St = torch.tensor(S, device="cuda")
+    outs = []
+    for sync in (False, True):
+        Wt = torch.full_like(St, float("nan"))
+        om, info = lib.fit(St, lam, tol, 500, w_out=Wt, sync_rewrites=sync, **shape)
+        torch.cuda.synchronize()
+        outs.append((om.cpu().numpy(), Wt.cpu().numpy(), info))
+    (a, wa, ia), (b, wb, ib) = outs
+    assert ia["w_in_lds"] == 0 and ia["code"] == 0
+    assert np.array_equal(a, b)
+    assert np.array_equal(wa, wb)
+    assert ia["sweeps"] == ib["sweeps"] and ia["moved_pairs"] == ib["moved_pairs"]
+
+
 # ------------------------------------------------------------------ ragged sizes
 
 RAGGED = [1, 2, 3, 4, 5, 6, 7, 16, 31, 33, 64, 65, 96, 97, 128, 129, 200, 257, 300]
