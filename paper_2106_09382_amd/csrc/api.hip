@@ -955,8 +955,11 @@ int batched_chunk(int B0, int B1, concord_input kind, const void *const *X, cons
     CK_HIP(hipMemcpyAsync(base + oMap, wmap.data(), sizeof(int) * Gtot, hipMemcpyHostToDevice,
                           stream));
     CK_HIP(hipEventRecord(ev[1], stream));
+    bool any_bg = false;
+    for (int q = 0; q < NB; ++q)
+        any_bg = any_bg || pr[q].ovl;
     CK_HIP(launch_sweep_batched<T>((const SweepParams<T> *)(base + oDesc),
-                                   (const int *)(base + oMap), Gtot, lds, threads, cpl,
+                                   (const int *)(base + oMap), Gtot, lds, threads, cpl, any_bg,
                                    stream));
     CK_HIP(hipEventRecord(ev[2], stream));
 

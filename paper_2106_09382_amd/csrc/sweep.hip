@@ -35,14 +35,16 @@ __global__ void __launch_bounds__(512) pcd_sweep_kernel(SweepParams<T> P)
 // step: by default they keep four columns per lane in flight (CPL) instead
 // of two.  A problem's workgroups may also split its columns into slices
 // (Gr x Gc per problem, from its descriptor).
-template <typename T, int CPL>
+// BG: 0 = every problem rewrites right after each step, 2 = each problem as
+// its descriptor's ovl says.
+template <typename T, int CPL, int BG>
 __global__ void __launch_bounds__(512)
     pcd_batched_kernel(const SweepParams<T> *__restrict__ descs, const int *__restrict__ wg_problem)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const SweepParams<T> P = descs[wg_problem[blockIdx.x]];
     const int g = (int)blockIdx.x - P.g0, G = P.Gr * P.Gc;
-    pcd_solve<T, false, 2, CPL, false, false, false, 2>(P, g, G, smem_raw);
+    pcd_solve<T, false, 2, CPL, false, false, false, BG>(P, g, G, smem_raw);
 }
 
 namespace {
@@ -94,12 +96,14 @@ hipError_t launch_sweep(const SweepParams<T> &P, int threads, hipStream_t stream
 
 template <typename T>
 hipError_t launch_sweep_batched(const SweepParams<T> *descs, const int *wg_problem, int G,
-                                size_t lds, int threads, int cpl, hipStream_t stream)
+                                size_t lds, int threads, int cpl, bool any_bg, hipStream_t stream)
 {
     if (cpl != 2 && cpl != 4)
         return hipErrorInvalidValue;
-    const void *fn = (cpl == 2) ? (const void *)pcd_batched_kernel<T, 2>
-                                : (const void *)pcd_batched_kernel<T, 4>;
+    const void *fn = (cpl == 2) ? (any_bg ? (const void *)pcd_batched_kernel<T, 2, 2>
+                                          : (const void *)pcd_batched_kernel<T, 2, 0>)
+                                : (any_bg ? (const void *)pcd_batched_kernel<T, 4, 2>
+                                          : (const void *)pcd_batched_kernel<T, 4, 0>);
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess)
         return e;
@@ -110,9 +114,9 @@ hipError_t launch_sweep_batched(const SweepParams<T> *descs, const int *wg_probl
 }
 
 template hipError_t launch_sweep_batched<float>(const SweepParams<float> *, const int *, int,
-                                                size_t, int, int, hipStream_t);
+                                                size_t, int, int, bool, hipStream_t);
 template hipError_t launch_sweep_batched<double>(const SweepParams<double> *, const int *, int,
-                                                 size_t, int, int, hipStream_t);
+                                                 size_t, int, int, bool, hipStream_t);
 template size_t sweep_lds_bytes<float>(const SweepParams<float> &);
 template size_t sweep_lds_bytes<double>(const SweepParams<double> &);
 template hipError_t launch_sweep<float>(const SweepParams<float> &, int, hipStream_t);
