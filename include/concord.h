@@ -77,7 +77,15 @@ typedef struct {
 typedef struct {
     int32_t row_groups;     /* workgroups sharing out the rows of W (0 = auto) */
     int32_t col_slices;     /* workgroups sharing out the columns of W (0 = auto) */
-    int32_t block_threads;  /* threads per workgroup, multiple of 64, <= 512 (0 = auto) */
+    /* Threads per workgroup, a multiple of 64: up to 512; or, with W in HBM
+     * and one row of W per thread, up to 1024 in FP32 and 768 in FP64 (the
+     * waves that hold no rows rewrite rows in the background; more of them
+     * finish a burst of rewrites sooner).  Wider requests, and wide ones with
+     * w_in_lds = 1, are CONCORD_EINVAL; p above row_groups x block_threads
+     * with a wide workgroup is CONCORD_ELAUNCH.  0 = auto: the widest (1024
+     * in FP32, 768 in FP64) with W in HBM when the rows fill at most half of
+     * its waves, else 512 (256 for a single workgroup). */
+    int32_t block_threads;
     int32_t w_in_lds;       /* -1/0 = auto, 1 = force W blocks in LDS, 2 = force W in HBM */
     int32_t pending_depth;  /* 0 = auto, else 2..8: updates a row holds before it is rewritten */
     double *delta_trace;    /* optional host array of maxit entries: delta of every sweep */
@@ -275,8 +283,8 @@ typedef struct {
  *   info       out (host, may be NULL)
  * The launch runs 2 row_groups x col_slices workgroups (by default each
  * population gets half the compute units).  Options (opts may be NULL):
- * row_groups, col_slices, block_threads, w_in_lds, pending_depth and
- * delta_trace as for concord_fit_ex; active_set, w_out and
+ * row_groups, col_slices, block_threads (at most 512 here), w_in_lds,
+ * pending_depth and delta_trace as for concord_fit_ex; active_set, w_out and
  * device_timestamps must be zero (CONCORD_EINVAL otherwise).
  * Returns CONCORD_OK, CONCORD_NOT_CONVERGED or a negative code.
  */

@@ -84,16 +84,22 @@ int max_shared_per_block()
 // workgroup; larger ones over a grid of Gr x Gc workgroups, one per CU (of
 // the 1 / cu_share of the CUs the solve gets), with W blocks in LDS when they
 // fit.  Rows of a workgroup are dealt to threads, at most two per thread.
+// wide_ok: the launch may use the wide sweep kernel (workgroups of more than
+// 512 threads, W in HBM); the joint kernel has only the 512-thread form.
 template <typename T>
-int choose_shape(int p, const concord_options *o, Shape *sh, int cu_share = 1)
+int choose_shape(int p, const concord_options *o, Shape *sh, int cu_share = 1,
+                 bool wide_ok = true)
 {
     const int cus = std::max(1, cu_count() / cu_share);
     int Gr = o ? o->row_groups : 0, Gc = o ? o->col_slices : 0;
     int threads = o ? o->block_threads : 0;
     int wl = o ? o->w_in_lds : 0;
     int depth = o ? o->pending_depth : 0;
-    if (Gr < 0 || Gc < 0 || threads < 0 || (threads % 64) != 0 || threads > 512 || depth < 0 ||
-        depth == 1 || depth > 8)
+    if (Gr < 0 || Gc < 0 || threads < 0 || (threads % 64) != 0 || depth < 0 || depth == 1 ||
+        depth > 8)
+        return CONCORD_EINVAL;
+    // more than 512 threads: the wide kernel, W in HBM
+    if (threads > 512 && (!wide_ok || threads > wide_threads<T>() || wl == 1))
         return CONCORD_EINVAL;
     if (Gr == 0 && Gc == 0) {
         if (p <= 96) {
@@ -114,11 +120,12 @@ int choose_shape(int p, const concord_options *o, Shape *sh, int cu_share = 1)
     sh->Gr = Gr;
     sh->Gc = Gc;
     sh->nr_max = (p + Gr - 1) / Gr;
+    const bool auto_threads = (threads == 0);
     if (threads == 0)
         threads = (Gr * Gc == 1) ? 256 : 512;
     sh->threads = threads;
     sh->rpt = (sh->nr_max + threads - 1) / threads;
-    if (sh->rpt > 2)
+    if (sh->rpt > 2 || (threads > 512 && sh->rpt > 1))
         return CONCORD_ELAUNCH;
     if (sh->rpt < 1)
         sh->rpt = 1;
@@ -141,10 +148,18 @@ int choose_shape(int p, const concord_options *o, Shape *sh, int cu_share = 1)
     const bool fits = lds_need(depth ? depth : 2, true) <= cap;
     if (wl == 1 && !fits)
         return CONCORD_EINVAL;
-    sh->w_lds = (wl == 1) ? 1 : (wl == 2 ? 0 : (fits ? 1 : 0));
+    sh->w_lds = (threads > 512 || wl == 2) ? 0 : (wl == 1 ? 1 : (fits ? 1 : 0));
     sh->depth = depth ? depth : (sh->w_lds ? 2 : 8);
     if (lds_need(sh->depth, sh->w_lds) > cap)
         return CONCORD_ELAUNCH;
+    // W in HBM: the wide kernel by default when the rows leave at least half
+    // of its waves to the background rewrites
+    const int wt = wide_threads<T>();
+    if (auto_threads && wide_ok && !sh->w_lds && Gr * Gc > 1 &&
+        sh->depth >= 4 && 2 * ((sh->nr_max + 63) / 64) <= wt / 64) {
+        sh->threads = wt;
+        sh->rpt = 1;
+    }
     return CONCORD_OK;
 }
 
@@ -202,29 +217,43 @@ int scratch_address(void **out)
 // kernel's last colour publishes for the first).
 int greedy_colouring(const int *edges, int ne, int p, std::vector<int> *part)
 {
-    std::vector<std::pair<int, int>> E((size_t)ne);
-    for (int e = 0; e < ne; ++e)
-        E[e] = {std::min(edges[2 * e], edges[2 * e + 1]), std::max(edges[2 * e], edges[2 * e + 1])};
-    std::sort(E.begin(), E.end());
-    std::vector<std::vector<uint64_t>> used((size_t)p);
-    std::vector<int> colour((size_t)ne);
-    int m = 0;
-    for (int e = 0; e < ne; ++e) {
-        std::vector<uint64_t> &ui = used[E[e].first], &uj = used[E[e].second];
-        int c = 0;
-        for (size_t w = 0;; ++w) {
-            const uint64_t a = w < ui.size() ? ui[w] : 0, b = w < uj.size() ? uj[w] : 0;
-            const uint64_t freeb = ~(a | b);
-            if (freeb) {
-                c = (int)(64 * w) + __builtin_ctzll(freeb);
-                break;
-            }
+    // the edges as (lo, hi) in lexicographic order: two stable counting passes,
+    // by hi and then by lo (the pairs are distinct, so the order is total)
+    const size_t n = (size_t)std::max(ne, 0);
+    std::vector<int> lo(n), hi(n), cnt((size_t)p + 1), byhi(n), ord(n), deg((size_t)p, 0);
+    for (size_t e = 0; e < n; ++e) {
+        lo[e] = std::min(edges[2 * e], edges[2 * e + 1]);
+        hi[e] = std::max(edges[2 * e], edges[2 * e + 1]);
+        ++deg[lo[e]];
+        ++deg[hi[e]];
+    }
+    auto pass = [&](const std::vector<int> &key, const int *in, int *out) {
+        std::fill(cnt.begin(), cnt.end(), 0);
+        for (size_t e = 0; e < n; ++e)
+            ++cnt[(size_t)key[e] + 1];
+        for (int v = 0; v < p; ++v)
+            cnt[(size_t)v + 1] += cnt[v];
+        for (size_t k = 0; k < n; ++k) {
+            const int e = in ? in[k] : (int)k;
+            out[cnt[key[e]]++] = e;
         }
-        const size_t w = (size_t)c / 64;
-        if (ui.size() <= w)
-            ui.resize(w + 1, 0);
-        if (uj.size() <= w)
-            uj.resize(w + 1, 0);
+    };
+    pass(hi, nullptr, byhi.data());
+    pass(lo, byhi.data(), ord.data());
+    // an edge's colour is below deg(lo) + deg(hi) - 1, so each vertex's used
+    // colours fit in W words
+    const int dmax = p > 0 ? *std::max_element(deg.begin(), deg.end()) : 0;
+    const size_t W = (size_t)(2 * dmax + 63) / 64 + 1;
+    std::vector<uint64_t> used((size_t)p * W, 0);
+    std::vector<int> colour(n);
+    int m = 0;
+    for (size_t k = 0; k < n; ++k) {
+        const int e = ord[k];
+        uint64_t *ui = &used[(size_t)lo[e] * W], *uj = &used[(size_t)hi[e] * W];
+        size_t w = 0;
+        while (~(ui[w] | uj[w]) == 0)
+            ++w;
+        const int c = (int)(64 * w) + __builtin_ctzll(~(ui[w] | uj[w]));
         ui[w] |= 1ull << (c % 64);
         uj[w] |= 1ull << (c % 64);
         colour[e] = c;
@@ -232,9 +261,9 @@ int greedy_colouring(const int *edges, int ne, int p, std::vector<int> *part)
     }
     m = std::max(m, 2);
     part->assign((size_t)m * p, -1);
-    for (int e = 0; e < ne; ++e) {
-        (*part)[(size_t)colour[e] * p + E[e].first] = E[e].second;
-        (*part)[(size_t)colour[e] * p + E[e].second] = E[e].first;
+    for (size_t e = 0; e < n; ++e) {
+        (*part)[(size_t)colour[e] * p + lo[e]] = hi[e];
+        (*part)[(size_t)colour[e] * p + hi[e]] = lo[e];
     }
     return m;
 }
@@ -1152,7 +1181,7 @@ int joint_impl(concord_input kind, const void *const X[2], const int64_t n[2], i
     if (opts && (opts->active_set || opts->w_out || opts->device_timestamps))
         return CONCORD_EINVAL;
     Shape sh;
-    int rc = choose_shape<T>(p, opts, &sh, 2);
+    int rc = choose_shape<T>(p, opts, &sh, 2, false);
     if (rc)
         return rc;
     const Circle C = Circle::make(p);

@@ -13,6 +13,9 @@
 // With both --y and --batched, the single solves run first and then one
 // repetition of the batch (tol 1e-5, maxit 500), in one process.
 //
+// Runs joined by --then (each written as above) are made in order in one
+// process; the first one that fails ends the process with its status.
+//
 // --copy runs one device-to-device copy of MIB mebibytes (the runtime's copy
 // kernel) and exits: a reference of known size for hardware byte counters.
 //
@@ -54,7 +57,8 @@ void usage()
                  "       concord_bench --batched DIR [--plan FILE] [--tol T] [--maxit K] "
                  "[--reps R] [--threads C] [--cpl K]\n"
                  "       concord_bench --backward --y FILE --n N --p P [--lam L] [--tol T] "
-                 "[--reps R]\n");
+                 "[--reps R]\n"
+                 "       concord_bench RUN --then RUN [--then RUN ...]\n");
 }
 
 // The batched workload from DIR, FP32, one launch per repetition.
@@ -409,7 +413,18 @@ int run(int argc, char **argv)
 // library issued is left for the runtime's exit-time teardown to retire.
 int main(int argc, char **argv)
 {
-    const int rc = run(argc, argv);
+    // "--then" separates runs made one after the other in this process, so
+    // one profiler run covers several workloads; the first failure ends it
+    int rc = 0;
+    std::vector<char *> seg{argv[0]};
+    for (int k = 1; k <= argc && rc == 0; ++k) {
+        if (k < argc && std::strcmp(argv[k], "--then") != 0) {
+            seg.push_back(argv[k]);
+            continue;
+        }
+        rc = run((int)seg.size(), seg.data());
+        seg.resize(1);
+    }
     (void)hipDeviceSynchronize();
     int dev = 0;
     hipMemPool_t pool = nullptr;

@@ -26,6 +26,15 @@ __global__ void __launch_bounds__(512) pcd_sweep_kernel(SweepParams<T> P)
     pcd_solve<T, WLDS, RPT, 2, ADJ, TAB, false, BG>(P, blockIdx.x, gridDim.x, smem_raw);
 }
 
+// The same solve in workgroups of up to wide_threads<T>() threads (W in HBM,
+// one row per thread); see wide_threads.
+template <typename T, bool ADJ, bool TAB, int BG>
+__global__ void __launch_bounds__(wide_threads<T>()) pcd_sweep_wide_kernel(SweepParams<T> P)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    pcd_solve<T, false, 1, 2, ADJ, TAB, false, BG>(P, blockIdx.x, gridDim.x, smem_raw);
+}
+
 // Many independent problems in one launch: workgroup blockIdx.x serves
 // problem wg_problem[blockIdx.x], as workgroup blockIdx.x - g0 of its Gr x Gc.
 // W stays in HBM here (one code path keeps the register budget of the
@@ -65,6 +74,13 @@ const void *pick_kernel(int rpt, int ovl)
     return (const void *)pcd_sweep_kernel<T, WLDS, 2, ADJ, TAB, 0>;
 }
 
+template <typename T, bool ADJ, bool TAB>
+const void *pick_wide_kernel(int ovl)
+{
+    return ovl ? (const void *)pcd_sweep_wide_kernel<T, ADJ, TAB, 1>
+               : (const void *)pcd_sweep_wide_kernel<T, ADJ, TAB, 0>;
+}
+
 }  // namespace
 
 template <typename T>
@@ -77,7 +93,13 @@ hipError_t launch_sweep(const SweepParams<T> &P, int threads, hipStream_t stream
     const void *fn;
     if (P.adj_g && P.part)
         return hipErrorInvalidValue;
-    if (P.adj_g)
+    if (threads > 512) {
+        if (P.w_lds || P.rpt > 1 || threads > wide_threads<T>())
+            return hipErrorInvalidValue;
+        fn = P.adj_g  ? pick_wide_kernel<T, true, false>(P.ovl)
+             : P.part ? pick_wide_kernel<T, false, true>(P.ovl)
+                      : pick_wide_kernel<T, false, false>(P.ovl);
+    } else if (P.adj_g)
         fn = P.w_lds ? pick_kernel<T, true, true, false>(P.rpt, 0)
                      : pick_kernel<T, false, true, false>(P.rpt, P.ovl);
     else if (P.part)

@@ -146,6 +146,20 @@ inline void set_overlap(SweepParams<T> &P, int threads, size_t lds_cap)
         P.ovl = 0;
 }
 
+// Widest workgroup of the single-problem sweep kernel (W in HBM, one row per
+// thread): the waves beyond the rows' rewrite rows in the background, and
+// more of them finish a burst of rewrites sooner.  The width is the largest
+// whose register budget holds the kernel with at most a few spilled words:
+// 1024 threads leave 128 VGPRs a wave (FP32 needs about that), 768 leave 168
+// (FP64).  Workgroups of at most 512 threads use the 512-thread kernel.
+template <typename T>
+constexpr int wide_threads()
+{
+    return sizeof(T) == 4 ? 1024 : 768;
+}
+
+// threads > 512 launches the wide kernel, which needs W in HBM, one row per
+// thread and threads <= wide_threads<T>().
 template <typename T>
 hipError_t launch_sweep(const SweepParams<T> &P, int threads, hipStream_t stream);
 

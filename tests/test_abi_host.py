@@ -132,6 +132,37 @@ def test_rows_per_thread_cap_returns_elaunch(lib, rows, cols, threads):
         assert rc == _lib.ELAUNCH
 
 
+@pytest.mark.parametrize("dt,threads,wl,want", [
+    (0, 1088, 0, "EINVAL"),    # FP32: at most 1024 threads
+    (1, 832, 0, "EINVAL"),     # FP64: at most 768 threads
+    (1, 1024, 0, "EINVAL"),
+    (0, 1024, 1, "EINVAL"),    # a wide workgroup keeps W in HBM
+    (0, 1024, 0, "ELAUNCH"),   # one row per thread: p = rows x threads + 1 does not fit
+    (1, 768, 0, "ELAUNCH"),
+])
+def test_wide_workgroups_are_checked_before_device_work(lib, dt, threads, wl, want):
+    """Workgroups of more than 512 threads (the wide sweep kernel) hold one row
+    of W per thread with W in HBM; requests outside that are refused while
+    the launch shape is chosen (the pointers here are not device memory)."""
+    from paper_2106_09382_amd import _lib
+    rows = 32
+    opts = _lib.ConcordOptions()
+    opts.row_groups, opts.col_slices, opts.block_threads, opts.w_in_lds = rows, 8, threads, wl
+    info = _lib.ConcordInfo()
+    rc = lib.concord_fit_ex(0, ctypes.c_void_p(0x1000), 0, rows * threads + 1, 0.1, 1e-6, 10, dt,
+                            None, ctypes.c_void_p(0x2000), ctypes.byref(info), None,
+                            ctypes.byref(opts))
+    assert rc == getattr(_lib, want)
+
+
+def test_joint_solve_has_no_wide_workgroups(lib):
+    from paper_2106_09382_amd import _lib
+    opts = _lib.ConcordOptions()
+    opts.block_threads = 1024
+    rc, _ = _fit_joint(lib, opts=opts, dt=0)
+    assert rc == _lib.EINVAL
+
+
 def test_gram_rejects_bad_sizes(lib):
     assert lib.concord_gram(None, 10, 10, 1, ctypes.c_void_p(0x10), None) == -1
     assert lib.concord_gram(ctypes.c_void_p(0x10), 0, 10, 1, ctypes.c_void_p(0x10), None) == -1
@@ -317,3 +348,21 @@ def test_struct_layouts_match_the_header(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(py), cname
         for fname, _ in py._fields_:
             assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
+
+
+def test_profiling_driver_rejects_bad_runs_before_device_work():
+    """concord_bench: an unknown flag prints the usage and exits 2; runs joined
+    by --then stop at the first one that fails, so the copy after it never
+    starts (it would print its size)."""
+    import subprocess
+    from paper_2106_09382_amd import build
+    if not os.path.exists(build.BENCH):
+        pytest.skip("concord_bench is not built")
+    r = subprocess.run([build.BENCH, "--bogus", "--then", "--copy", "1"],
+                       capture_output=True, text=True, timeout=60)
+    assert r.returncode == 2
+    assert "usage: concord_bench" in r.stderr and "--then RUN" in r.stderr
+    assert "copy_bytes" not in r.stdout
+    r = subprocess.run([build.BENCH, "--y", "/nonexistent", "--n", "0", "--p", "5"],
+                       capture_output=True, text=True, timeout=60)
+    assert r.returncode == 2 and "usage: concord_bench" in r.stderr

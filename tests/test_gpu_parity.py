@@ -175,6 +175,63 @@ def test_background_rewrites_match_synchronous_bit_for_bit(lib, config, shape):
     assert ia["sweeps"] == ib["sweeps"] and ia["moved_pairs"] == ib["moved_pairs"]
 
 
+# Workgroups wider than 512 threads (W in HBM, one row per thread, the waves
+# without rows rewriting in the background): the same bits as 512 threads, in
+# plain, active-set and adjoint sweeps.
+WIDE_CASES = [
+    (1, "f64", dict(w_in_lds=2, block_threads=768)),
+    (2, "f64", dict(w_in_lds=2, block_threads=768)),
+    (2, "f64", dict(w_in_lds=2, block_threads=640, sync_rewrites=True)),
+    (2, "f64", dict(block_threads=768, active_set=True)),
+    (2, "f32", dict(w_in_lds=2, block_threads=1024)),
+    (2, "f32", dict(w_in_lds=2, block_threads=1024, row_groups=16, col_slices=4,
+                    pending_depth=6)),
+]
+
+
+@pytest.mark.parametrize("config,dt,shape", WIDE_CASES,
+                         ids=[f"{c}-{d}-{s}" for c, d, s in WIDE_CASES])
+def test_wide_workgroups_match_512_threads_bit_for_bit(lib, config, dt, shape):
+    pr = _problem(config)
+    lam, tol = (0.3, 1e-8) if config == 1 else (0.2, 1e-7)
+    St = torch.tensor(pr["S"], device="cuda",
+                      dtype=torch.float64 if dt == "f64" else torch.float32)
+    outs = []
+    for threads in (shape["block_threads"], 512):
+        kw = dict(shape, block_threads=threads, w_in_lds=2)
+        Wt = torch.full_like(St, float("nan"))
+        om, info = lib.fit(St, lam, tol, 500, w_out=Wt, **kw)
+        torch.cuda.synchronize()
+        outs.append((om.cpu().numpy(), Wt.cpu().numpy(), info))
+    (a, wa, ia), (b, wb, ib) = outs
+    assert ia["block_threads"] == shape["block_threads"] and ib["block_threads"] == 512
+    assert ia["w_in_lds"] == 0 and ia["code"] == 0
+    assert np.array_equal(a, b)
+    assert np.array_equal(wa, wb)
+    assert ia["sweeps"] == ib["sweeps"] and ia["moved_pairs"] == ib["moved_pairs"]
+    assert ia["active_sweeps"] == ib["active_sweeps"]
+
+
+def test_wide_adjoint_sweeps_match_512_threads_bit_for_bit(lib):
+    pr = _problem(2)
+    St = torch.tensor(pr["S"], device="cuda")
+    om, _ = lib.fit(St, 0.2, 1e-10, 2000)
+    G = torch.tensor(np.random.default_rng(11).standard_normal(St.shape), device="cuda")
+    G = G + G.T
+    outs = []
+    for threads in (768, 512):
+        gS, glam, info = lib.backward(St, om, G, 1e-10, 2000, w_in_lds=2, block_threads=threads)
+        torch.cuda.synchronize()
+        outs.append((gS.cpu().numpy(), glam, info))
+    (a, la, ia), (b, lb, ib) = outs
+    assert ia["block_threads"] == 768 and ib["block_threads"] == 512
+    assert np.array_equal(a, b) and ia["sweeps"] == ib["sweeps"]
+    # dL/dlam sums the active set's terms with atomics: the order of the
+    # additions varies from call to call (a few units in the 14th digit at
+    # p = 1001), the terms do not
+    assert la == pytest.approx(lb, rel=1e-12)
+
+
 # ------------------------------------------------------------------ ragged sizes
 
 RAGGED = [1, 2, 3, 4, 5, 6, 7, 16, 31, 33, 64, 65, 96, 97, 128, 129, 200, 257, 300]
