@@ -129,9 +129,10 @@ def cpu_wform_baseline(S, p: int, lam: float, gpu_bytes: float, budget_s: float)
             "host_threads": os.cpu_count()}
 
 
-def measured_traffic(p: int, n: int, lam: float, dtype: str):
+def measured_traffic(p: int, n: int, lam: float, dtype: str, kernel: str):
     """HBM bytes per sweep-kernel launch from the committed rocprofv3 counter
-    runs, or None when they were taken on another workload or kernel source."""
+    runs, or None when they were taken on another workload, kernel or kernel
+    source."""
     import hashlib
     try:
         rec = json.load(open(os.path.join(ROOT, "profiles", "pcd_sweep_traffic.json")))
@@ -140,6 +141,8 @@ def measured_traffic(p: int, n: int, lam: float, dtype: str):
     except (OSError, ValueError):
         return None
     if hashlib.sha256(src).hexdigest()[:16] != rec.get("sweep_src_sha256_16"):
+        return None
+    if rec.get("kernel") != kernel:
         return None
     if (p, n, lam, dtype) != (5000, 2000, 0.1, "f64"):
         return None
@@ -679,7 +682,9 @@ def main() -> int:
     last = infos[-1]
     # measured HBM bytes of one sweep-kernel launch (rocprofv3 FETCH_SIZE +
     # WRITE_SIZE on this source), beside the algorithmic account above
-    traffic = measured_traffic(args.p, args.n, args.lam, args.dtype)
+    # workgroups of more than 512 threads run the wide form of the sweep kernel
+    kernel = "pcd_sweep_wide_kernel" if last["block_threads"] > 512 else "pcd_sweep_kernel"
+    traffic = measured_traffic(args.p, args.n, args.lam, args.dtype, kernel)
     res = {
         "metric": "sweep GB/s (algorithmic) of a CONCORD-PCD solve to tolerance at p=5000, n=2000",
         "value": bytes_total / wall / 1e9,
@@ -713,7 +718,7 @@ def main() -> int:
         "moved_pairs_per_sweep": last["moved_pairs"] / max(sweeps, 1),
         "bytes_per_sweep": bytes_launch / max(sweeps, 1),
         "roofline": {
-            "kernel": "pcd_sweep_kernel",
+            "kernel": kernel,
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,

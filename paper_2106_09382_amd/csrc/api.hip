@@ -107,6 +107,15 @@ int choose_shape(int p, const concord_options *o, Shape *sh, int cu_share = 1,
         } else {
             Gc = p < 512 ? 1 : (p < 2048 ? 2 : 8);
             Gr = std::max(1, cus / Gc);
+            // Without wide workgroups (the joint solve): fewer column slices
+            // until a workgroup's rows fill at most half of its waves, so that
+            // the others rewrite rows in the background (two populations at
+            // p = 5000: 32 x 4 per population instead of 16 x 8)
+            const int waves = (threads ? threads : 512) / 64;
+            while (!wide_ok && Gc > 2 && 2 * (((p + Gr - 1) / Gr + 63) / 64) > waves) {
+                Gc /= 2;
+                Gr = std::max(1, cus / Gc);
+            }
         }
     } else if (Gr == 0) {
         Gr = std::max(1, cus / Gc);
