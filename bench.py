@@ -171,27 +171,29 @@ def batched_measurement(plain_all: bool) -> dict:
 
     last = {}
 
-    def run_batch(pw=None, pc=None, cpl=0):
+    def run_batch(pw=None, pc=None, cpl=0, threads=0):
         with warnings.catch_warnings():
             warnings.simplefilter("ignore")
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             outs, infos, code = _lib.fit_batched(Xs, lams, tol, maxit, kind="Y", check=False,
                                                  problem_workgroups=pw, problem_col_slices=pc,
-                                                 cols_per_lane=cpl)
+                                                 cols_per_lane=cpl, block_threads=threads)
             torch.cuda.synchronize()
             wall = time.perf_counter() - t0
         if code < 0:
             raise RuntimeError(f"batched solve failed with status {code}")
-        last[(None if pw is None else tuple(pw), None if pc is None else tuple(pc), cpl)] = \
-            (infos, code)
+        last[(None if pw is None else tuple(pw), None if pc is None else tuple(pc), cpl,
+              threads or 512)] = (infos, code)
         return infos, wall
 
     total = torch.cuda.get_device_properties(0).multi_processor_count
-    best = autotune.search(run_batch, [int(x) for x in ps], total, log=log)
+    # FP32 batch: the wide workgroups hold 1024 threads
+    best = autotune.search(run_batch, [int(x) for x in ps], total, wide_threads=1024, log=log)
     wall_default = best["trials"][0]["wall_s"]
     tuned = best["problem_workgroups"]
-    infos, code = last[(tuple(tuned), tuple(best["problem_col_slices"]), best["cols_per_lane"])]
+    infos, code = last[(tuple(tuned), tuple(best["problem_col_slices"]), best["cols_per_lane"],
+                        best["block_threads"])]
     wall = best["wall_s"]
     sweeps = sum(i["sweeps"] for row in infos for i in row)
     moved = np.array([sum(i["moved_pairs"] for i in row) for row in infos], dtype=float)
@@ -231,11 +233,12 @@ def batched_measurement(plain_all: bool) -> dict:
         "wall_s": wall,
         "wall_s_builtin_plan": wall_default,
         "plan": ("autotuned: workgroups dealt by measured per-problem work, each problem's "
-                 "split into row groups x column slices and the columns per lane in row "
-                 "rewrites picked from measured runs"),
+                 "split into row groups x column slices, the columns per lane in row "
+                 "rewrites and the workgroup width picked from measured runs"),
         "tuned_plan": {"problem_workgroups": [int(x) for x in tuned],
                        "problem_col_slices": [int(x) for x in best["problem_col_slices"]],
-                       "cols_per_lane": int(best["cols_per_lane"]), "block_threads": 512,
+                       "cols_per_lane": int(best["cols_per_lane"]),
+                       "block_threads": int(best["block_threads"]),
                        "work_model_exponent": best["work_model_exponent"]},
         "autotune_trials": [{"tag": t["tag"], "wall_s": t["wall_s"]} for t in best["trials"]],
         "solves_per_s": B * L / wall,

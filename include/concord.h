@@ -171,12 +171,17 @@ int concord_fit_ex(concord_input kind, const void *X, int64_t n, int64_t p, doub
 /* Launch options of the batched solver (all 0 = defaults). */
 typedef struct {
     int32_t workgroups;     /* workgroups of one launch (0 = one per compute unit); at most
-                               one per compute unit at 512 threads, two at 256 or fewer */
-    int32_t block_threads;  /* threads per workgroup, multiple of 64, <= 512 (0 = 512) */
+                               one per compute unit above 256 threads, two at 256 or fewer */
+    /* Threads per workgroup, a multiple of 64: up to 512, each thread holding
+     * up to two rows of W; or wide workgroups, up to 1024 in FP32 and 768 in
+     * FP64, each thread holding one row (more problems then leave half of
+     * their waves to background rewrites).  0 = 512.  R = rows a workgroup
+     * holds: 2 x block_threads up to 512 threads, block_threads above. */
+    int32_t block_threads;
     int32_t pending_depth;  /* 2..8 row updates held before a row is rewritten (0 = 8) */
     int32_t cols_per_lane;  /* columns of W each lane carries in a row rewrite: 2 or 4 (0 = 4) */
     /* Optional host array of B workgroup counts, one per problem (each at
-     * least ceil(p_b / (2 * block_threads)) row groups' worth and at most
+     * least ceil(p_b / R) row groups' worth and at most
      * p_b, summing to at most `workgroups`): all problems then share one
      * launch with these counts instead of the built-in plan.  NULL = built-in
      * plan. */
@@ -186,7 +191,7 @@ typedef struct {
      * a grid of problem_workgroups[b] / c_b row groups x c_b column slices,
      * each workgroup holding its row group's rows of W in one slice of the
      * columns (c_b must divide the workgroup count, be <= p_b, and leave
-     * ceil(p_b / row groups) <= 2 * block_threads).  NULL = one slice each. */
+     * ceil(p_b / row groups) <= R).  NULL = one slice each. */
     const int32_t *problem_col_slices;
     /* 1 = row rewrites right after their step, as concord_options.sync_rewrites */
     int32_t sync_rewrites;

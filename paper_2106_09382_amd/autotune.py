@@ -20,10 +20,16 @@ from __future__ import annotations
 import math
 
 
+def max_rows(threads: int) -> int:
+    """Rows of W one workgroup holds: two per thread, one per thread in a
+    wide workgroup (more than 512 threads)."""
+    return threads if threads > 512 else 2 * threads
+
+
 def min_workgroups(p: int, threads: int = 512, col_slices: int = 1) -> int:
-    """Fewest workgroups a problem of size p needs (two rows per thread in
+    """Fewest workgroups a problem of size p needs (max_rows(threads) rows in
     each row group), for a given number of column slices."""
-    return max(1, -(-p // (2 * threads))) * col_slices
+    return max(1, -(-p // max_rows(threads))) * col_slices
 
 
 def plan(ps, work, total: int, threads: int = 512, slices=None) -> list[int]:
@@ -75,16 +81,18 @@ def _slices_ok(p: int, G: int, c: int, threads: int) -> bool:
     if c < 1 or c > p or G % c:
         return False
     gr = G // c
-    return -(-p // gr) <= 2 * threads and gr * 8 <= p
+    return -(-p // gr) <= max_rows(threads) and gr * 8 <= p
 
 
 def search(run, ps, total: int, threads: int = 512, cpls=(4, 2), slice_options=(2,),
-           log=None) -> dict:
+           wide_threads: int | None = None, log=None) -> dict:
     """Measured search for the batch's launch plan.
 
-    run(problem_workgroups, problem_col_slices, cols_per_lane) runs the whole
-    batch once and returns (infos, wall_seconds); problem_workgroups None
-    means the built-in plan.  The search:
+    run(problem_workgroups, problem_col_slices, cols_per_lane[, threads])
+    runs the whole batch once and returns (infos, wall_seconds);
+    problem_workgroups None means the built-in plan, and threads (passed
+    only for the wide trials) the workgroup width, else `threads`.  The
+    search:
 
     1. runs the built-in plan and deals the workgroups by its measured work;
     2. for each candidate number of column slices, deals the workgroups
@@ -96,17 +104,23 @@ def search(run, ps, total: int, threads: int = 512, cpls=(4, 2), slice_options=(
        compared fairly);
     3. re-deals the workgroups by the work measured at the chosen splits,
        then runs that plan with each candidate columns-per-lane and keeps the
-       faster batch.
+       faster batch;
+    4. with `wide_threads`, runs wide workgroups (one row per thread, so that
+       more problems rewrite rows in the background) with the best columns
+       per lane, dealt by the measured work and then re-dealt by the work
+       measured in the wide run.
 
     Returns {"problem_workgroups", "problem_col_slices", "cols_per_lane",
-    "wall_s", "trials"}: the best plan found and a record of every run.
+    "block_threads", "wall_s", "trials"}: the best plan found and a record
+    of every run.
     """
     say = log or (lambda *a: None)
     trials = []
 
-    def trial(tag, pw, pc, cpl):
-        infos, wall = run(pw, pc, cpl)
+    def trial(tag, pw, pc, cpl, th=None):
+        infos, wall = run(pw, pc, cpl) if th is None else run(pw, pc, cpl, th)
         trials.append({"tag": tag, "cols_per_lane": cpl, "wall_s": wall,
+                       "block_threads": threads if th is None else th,
                        "problem_workgroups": None if pw is None else list(pw),
                        "problem_col_slices": None if pc is None else list(pc)})
         say(f"autotune: {tag}: {wall:.2f} s")
@@ -119,7 +133,7 @@ def search(run, ps, total: int, threads: int = 512, cpls=(4, 2), slice_options=(
     C = [1] * B
     infos, wall = trial("dealt by measured work", G, C, cpl0)
     best = {"problem_workgroups": list(G), "problem_col_slices": list(C), "cols_per_lane": cpl0,
-            "wall_s": wall}
+            "block_threads": threads, "wall_s": wall}
     work = problem_work(infos)
     for c in slice_options:
         # problems large enough for c slices of at least 8 rows per row group,
@@ -148,7 +162,23 @@ def search(run, ps, total: int, threads: int = 512, cpls=(4, 2), slice_options=(
                                 G2, C2, cpl)
         if wall_f < best["wall_s"]:
             best = {"problem_workgroups": list(G2), "problem_col_slices": list(C2),
-                    "cols_per_lane": cpl, "wall_s": wall_f}
+                    "cols_per_lane": cpl, "block_threads": threads, "wall_s": wall_f}
+    if wide_threads and sum(min_workgroups(p, wide_threads) for p in ps) <= total:
+        cpl = best["cols_per_lane"]
+        C1 = [1] * B
+        Gw = plan(ps, work, total, wide_threads)
+        infos_w, wall_w = trial(f"{wide_threads}-thread workgroups, dealt by measured work", Gw,
+                                C1, cpl, wide_threads)
+        cands = [(wall_w, Gw)]
+        Gw2 = plan(ps, problem_work(infos_w), total, wide_threads)
+        if Gw2 != Gw:
+            _, wall_w2 = trial(f"{wide_threads}-thread workgroups, re-dealt by their own work",
+                               Gw2, C1, cpl, wide_threads)
+            cands.append((wall_w2, Gw2))
+        for wall_c, Gc_ in cands:
+            if wall_c < best["wall_s"]:
+                best = {"problem_workgroups": list(Gc_), "problem_col_slices": list(C1),
+                        "cols_per_lane": cpl, "block_threads": wide_threads, "wall_s": wall_c}
     best["trials"] = trials
     best["slices_used"] = sorted({int(c) for c in best["problem_col_slices"]})
     best["work_model_exponent"] = _fit_exponent(ps, problem_work(infos))

@@ -802,14 +802,14 @@ int merge_status(int acc, int s)
 // like that (smaller problems need more sweeps), which is what the measured
 // per-problem device times of such batches follow.  Returns false when the
 // minimum does not fit.
-bool plan_workgroups(const std::vector<int> &ps, int total, int threads, std::vector<int> *G)
+bool plan_workgroups(const std::vector<int> &ps, int total, int max_rows, std::vector<int> *G)
 {
     const int B = (int)ps.size();
     G->assign(B, 1);
     long long used = 0;
     std::vector<double> w(B);
     for (int b = 0; b < B; ++b) {
-        (*G)[b] = std::max(1, (ps[b] + 2 * threads - 1) / (2 * threads));
+        (*G)[b] = std::max(1, (ps[b] + max_rows - 1) / max_rows);
         used += (*G)[b];
         w[b] = pow((double)ps[b], 1.55);
     }
@@ -969,7 +969,7 @@ int batched_chunk(int B0, int B1, concord_input kind, const void *const *X, cons
         D.nr_max = P.nr;
         D.nc_max = P.nc;
         D.depth = depth;
-        D.rpt = 2;
+        D.rpt = (threads > 512) ? 1 : 2;
         D.ovl = P.ovl;
         D.lam = (T)hl[(size_t)q * L];
         D.tol = (T)tol;
@@ -996,9 +996,14 @@ int batched_chunk(int B0, int B1, concord_input kind, const void *const *X, cons
     bool any_bg = false;
     for (int q = 0; q < NB; ++q)
         any_bg = any_bg || pr[q].ovl;
-    CK_HIP(launch_sweep_batched<T>((const SweepParams<T> *)(base + oDesc),
-                                   (const int *)(base + oMap), Gtot, lds, threads, cpl, any_bg,
-                                   stream));
+    if (threads > 512)
+        CK_HIP(launch_sweep_batched_wide<T>((const SweepParams<T> *)(base + oDesc),
+                                            (const int *)(base + oMap), Gtot, lds, threads, cpl,
+                                            any_bg, stream));
+    else
+        CK_HIP(launch_sweep_batched<T>((const SweepParams<T> *)(base + oDesc),
+                                       (const int *)(base + oMap), Gtot, lds, threads, cpl,
+                                       any_bg, stream));
     CK_HIP(hipEventRecord(ev[2], stream));
 
     // Readback: status words, per-sweep reductions and per-lambda records.
@@ -1111,16 +1116,19 @@ int batched_impl(int B, concord_input kind, const void *const *X, const int64_t 
     if (o && (o->workgroups < 0 || o->block_threads < 0 || o->pending_depth < 0 ||
               o->cols_per_lane < 0))
         return CONCORD_EINVAL;
-    // co-residency of the persistent launch: one 512-thread workgroup per
-    // CU, or two of at most 256 threads
+    // co-residency of the persistent launch: one workgroup of up to 512
+    // threads (or a wide one, up to wide_threads<T>(), one row per thread)
+    // per CU, or two of at most 256 threads
     const int per_cu = (threads <= 256) ? 2 : 1;
-    if (total > per_cu * cus || threads % 64 != 0 || threads > 512 || depth < 2 || depth > 8 ||
-        (cpl != 2 && cpl != 4))
+    if (total > per_cu * cus || threads % 64 != 0 || threads > wide_threads<T>() || depth < 2 ||
+        depth > 8 || (cpl != 2 && cpl != 4))
         return CONCORD_EINVAL;
+    // rows of W a workgroup can hold: two per thread, one in a wide workgroup
+    const int max_rows = (threads > 512 ? 1 : 2) * threads;
     // Problems go in order into launches of at most `total` workgroups.
     std::vector<int> minG(B);
     for (int b = 0; b < B; ++b)
-        minG[b] = std::max(1, (int)((pv[b] + 2 * threads - 1) / (2 * threads)));
+        minG[b] = std::max(1, (int)((pv[b] + max_rows - 1) / max_rows));
     const int32_t *fixed = o ? o->problem_workgroups : nullptr;
     if (fixed) {
         long long sum = 0;
@@ -1142,7 +1150,7 @@ int batched_impl(int B, concord_input kind, const void *const *X, const int64_t 
             if (c < 1 || c > pv[b] || fixed[b] % c != 0)
                 return CONCORD_EINVAL;
             const long long gr = fixed[b] / c;
-            if ((pv[b] + gr - 1) / gr > 2ll * threads)  // two rows per thread at most
+            if ((pv[b] + gr - 1) / gr > max_rows)
                 return CONCORD_EINVAL;
             Cb[b] = c;
         }
@@ -1159,7 +1167,7 @@ int batched_impl(int B, concord_input kind, const void *const *X, const int64_t 
         std::vector<int> ps(pv + b0, pv + b1), G;
         if (fixed)
             G.assign(fixed + b0, fixed + b1);
-        else if (!plan_workgroups(ps, total, threads, &G))
+        else if (!plan_workgroups(ps, total, max_rows, &G))
             return CONCORD_ELAUNCH;
         for (int b = b0; b < b1; ++b)
             Gb[b] = G[b - b0];

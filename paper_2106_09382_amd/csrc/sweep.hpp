@@ -172,6 +172,13 @@ template <typename T>
 hipError_t launch_sweep_batched(const SweepParams<T> *descs, const int *wg_problem, int G,
                                 size_t lds, int threads, int cpl, bool any_bg, hipStream_t stream);
 
+// The same over workgroups of 513..wide_threads<T>() threads, one row per
+// thread (every descriptor's rpt is 1).
+template <typename T>
+hipError_t launch_sweep_batched_wide(const SweepParams<T> *descs, const int *wg_problem, int G,
+                                     size_t lds, int threads, int cpl, bool any_bg,
+                                     hipStream_t stream);
+
 // Joint estimation: one cooperative launch of 2 G workgroups, population 0 on
 // the first G (P0) and population 1 on the rest (P1); G = Gr * Gc of both.
 template <typename T>

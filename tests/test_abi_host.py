@@ -201,6 +201,39 @@ def test_batched_invalid_arguments_return_einval(lib):
     assert _fit_batched(lib, dt=5) == -1
 
 
+def _fit_batched_ex(lib, opts, B=2, p=8, dt=1):
+    from paper_2106_09382_amd import _lib
+    vp = ctypes.c_void_p
+    L = 3
+    return lib.concord_fit_batched_ex(
+        B, 0, (vp * B)(*([0x1000] * B)), None, (ctypes.c_int64 * B)(*([p] * B)), L,
+        (ctypes.c_double * (B * L))(*([0.1] * (B * L))), 1e-6, 10, dt,
+        (vp * (B * L))(*([0x2000] * (B * L))), None, None, ctypes.byref(opts))
+
+
+@pytest.mark.parametrize("dt,threads,want", [(0, 1088, "EINVAL"), (1, 832, "EINVAL"),
+                                             (1, 1024, "EINVAL")])
+def test_batched_wide_workgroups_are_bounded(lib, dt, threads, want):
+    """The batch's workgroups reach 1024 threads in FP32 and 768 in FP64
+    (one row per thread); wider is refused before any device work."""
+    from paper_2106_09382_amd import _lib
+    opts = _lib.ConcordBatchOptions()
+    opts.block_threads = threads
+    assert _fit_batched_ex(lib, opts, dt=dt) == getattr(_lib, want)
+
+
+def test_batched_wide_workgroups_hold_one_row_per_thread(lib):
+    """With 768 threads a workgroup holds at most 768 rows: a problem of 1537
+    rows on 2 workgroups is refused before any device work (512-thread
+    workgroups, two rows per thread, would hold it)."""
+    from paper_2106_09382_amd import _lib
+    opts = _lib.ConcordBatchOptions()
+    opts.block_threads = 768
+    pw = (ctypes.c_int32 * 2)(2, 2)
+    opts.problem_workgroups = pw
+    assert _fit_batched_ex(lib, opts, p=1537) == _lib.EINVAL
+
+
 def test_autotune_plan_deals_by_work():
     from paper_2106_09382_amd import autotune
     ps = [200, 1500, 3000, 50]
@@ -284,6 +317,43 @@ def test_autotune_search_keeps_what_measures_faster():
     assert any(t["problem_workgroups"] == slow["problem_workgroups"]
                and t["problem_col_slices"] == slow["problem_col_slices"]
                and t["wall_s"] == slow["wall_s"] for t in slow["trials"])
+
+
+def test_autotune_search_tries_wide_workgroups():
+    """With wide_threads, the search also runs wide workgroups (one row per
+    thread) dealt by the measured work, and keeps them only if the batch runs
+    faster; the wide plan gives every problem at least ceil(p / threads)
+    workgroups of one slice."""
+    from paper_2106_09382_amd import autotune
+    assert autotune.max_rows(512) == 1024 and autotune.max_rows(1024) == 1024
+    assert autotune.min_workgroups(2000, 768) == 3 and autotune.min_workgroups(2000, 512) == 2
+    ps = [300, 800, 2500, 3000]
+    base = {300: 1.0, 800: 4.0, 2500: 30.0, 3000: 40.0}
+
+    def model(speed):
+        seen = []
+
+        def run(pw, pc, cpl, threads=512):
+            seen.append(threads)
+            pw = pw or [8] * len(ps)
+            pc = pc or [1] * len(ps)
+            f = speed if threads > 512 else 1.0
+            infos = [[{"sweep_ms": base[p] * f / g, "row_groups": g // c, "col_slices": c}]
+                     for p, g, c in zip(ps, pw, pc)]
+            return infos, max(r[0]["sweep_ms"] for r in infos)
+        return run, seen
+
+    run, seen = model(0.8)
+    best = autotune.search(run, ps, 64, slice_options=(), wide_threads=1024)
+    assert 1024 in seen and best["block_threads"] == 1024
+    assert best["problem_col_slices"] == [1] * len(ps)
+    for p, g in zip(ps, best["problem_workgroups"]):
+        assert g >= autotune.min_workgroups(p, 1024)
+    assert sum(best["problem_workgroups"]) <= 64
+    run, seen = model(1.5)
+    best = autotune.search(run, ps, 64, slice_options=(), wide_threads=1024)
+    assert 1024 in seen and best["block_threads"] == 512
+    assert all(t["block_threads"] in (512, 1024) for t in best["trials"])
 
 
 def _fit_joint(lib, opts=None, **kw):

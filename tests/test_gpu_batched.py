@@ -334,6 +334,28 @@ def test_explicit_and_autotuned_plans_give_the_same_bits(lib):
     assert bad == -1
 
 
+@pytest.mark.parametrize("dt,threads,cpl", [("f64", 768, 2), ("f64", 640, 4), ("f32", 1024, 4),
+                                             ("f32", 1024, 2)])
+def test_wide_workgroups_give_the_same_bits(lib, dt, threads, cpl):
+    """Workgroups wider than 512 threads hold one row per thread and rewrite
+    rows in the background in more problems: the same iterates, bit for bit,
+    as 512-thread workgroups (two rows per thread)."""
+    probs = _small_batch()
+    dtype = torch.float64 if dt == "f64" else torch.float32
+    tol = TOL if dt == "f64" else 1e-5
+    mats = [pr["S"] for pr in probs]
+    ref, rinfo, rcode = _run(lib, mats, LAMS, tol, MAXIT, dtype=dtype)
+    got, infos, code = _run(lib, mats, LAMS, tol, MAXIT, dtype=dtype, block_threads=threads,
+                            cols_per_lane=cpl)
+    assert code == rcode
+    for b in range(len(probs)):
+        assert infos[b][0]["block_threads"] == threads
+        for l in range(len(LAMS)):
+            assert np.array_equal(got[b][l], ref[b][l]), (b, l)
+            assert infos[b][l]["sweeps"] == rinfo[b][l]["sweeps"]
+            assert infos[b][l]["nnz_upper"] == rinfo[b][l]["nnz_upper"]
+
+
 @pytest.mark.parametrize("threads,cpl", [(512, 2), (256, 4), (256, 2)])
 def test_column_slices_and_rewrite_width_give_the_same_bits(lib, threads, cpl):
     """Problems split into row groups x column slices, narrower workgroups
