@@ -40,6 +40,27 @@ __global__ void support_edges_kernel(const T *__restrict__ omega, int p, int *__
     }
 }
 
+__global__ void fill_int_kernel(int *__restrict__ x, long long n, int v)
+{
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
+         e += (long long)gridDim.x * blockDim.x)
+        x[e] = v;
+}
+
+// Each edge writes its two table entries; a colour's edges share no vertex,
+// so every entry is written at most once.
+__global__ void partner_table_kernel(const int *__restrict__ edges, const int *__restrict__ colour,
+                                     int ne, int p, int *__restrict__ part)
+{
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < ne;
+         e += (long long)gridDim.x * blockDim.x) {
+        const int i = edges[2 * e], j = edges[2 * e + 1];
+        const long long row = (long long)colour[e] * p;
+        part[row + i] = j;
+        part[row + j] = i;
+    }
+}
+
 // Dense Omega from the copies of column slice 0: omega_ij at colour r of
 // row i's table entry, omega_ii per row.  Entries in no colour stay 0.
 template <typename T>
@@ -117,6 +138,20 @@ hipError_t launch_support_edges(const T *omega, int p, int *count, int *edges, l
 {
     hipLaunchKernelGGL(support_edges_kernel<T>, dim3(grid_for((long long)p * p, 4096)),
                        dim3(kThreads), 0, st, omega, p, count, edges, cap);
+    return hipGetLastError();
+}
+
+hipError_t launch_partner_table(const int *edges, const int *colour, int ne, int p, int m,
+                                int *part, hipStream_t st)
+{
+    const long long n = (long long)m * p;
+    hipLaunchKernelGGL(fill_int_kernel, dim3(grid_for(n, 4096)), dim3(kThreads), 0, st, part, n,
+                       -1);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || ne <= 0)
+        return e;
+    hipLaunchKernelGGL(partner_table_kernel, dim3(grid_for(ne, 4096)), dim3(kThreads), 0, st,
+                       edges, colour, ne, p, part);
     return hipGetLastError();
 }
 

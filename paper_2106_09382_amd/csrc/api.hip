@@ -221,10 +221,11 @@ int scratch_address(void **out)
 
 // Greedy edge colouring of the support (edges i < j, in any order): edges in
 // lexicographic order each take the smallest colour neither endpoint has
-// used.  Writes the m x p partner table (part[c * p + i] = partner of i in
-// colour c, -1 idle) and returns m, padded to at least 2 colours (the sweep
-// kernel's last colour publishes for the first).
-int greedy_colouring(const int *edges, int ne, int p, std::vector<int> *part)
+// used.  Writes each edge's colour (colour[e] for edge e of the list as
+// given) and returns the number of colours m, padded to at least 2 (the
+// sweep kernel's last colour publishes for the first); the partner table is
+// built from the colours on the device.
+int greedy_colouring(const int *edges, int ne, int p, std::vector<int> *colour_out)
 {
     // the edges as (lo, hi) in lexicographic order: two stable counting passes,
     // by hi and then by lo (the pairs are distinct, so the order is total)
@@ -254,7 +255,8 @@ int greedy_colouring(const int *edges, int ne, int p, std::vector<int> *part)
     const int dmax = p > 0 ? *std::max_element(deg.begin(), deg.end()) : 0;
     const size_t W = (size_t)(2 * dmax + 63) / 64 + 1;
     std::vector<uint64_t> used((size_t)p * W, 0);
-    std::vector<int> colour(n);
+    std::vector<int> &colour = *colour_out;
+    colour.assign(n, 0);
     int m = 0;
     for (size_t k = 0; k < n; ++k) {
         const int e = ord[k];
@@ -268,13 +270,7 @@ int greedy_colouring(const int *edges, int ne, int p, std::vector<int> *part)
         colour[e] = c;
         m = std::max(m, c + 1);
     }
-    m = std::max(m, 2);
-    part->assign((size_t)m * p, -1);
-    for (size_t e = 0; e < n; ++e) {
-        (*part)[(size_t)colour[e] * p + lo[e]] = hi[e];
-        (*part)[(size_t)colour[e] * p + hi[e]] = lo[e];
-    }
-    return m;
+    return std::max(m, 2);
 }
 
 // ext_ws == nullptr: the workspace is allocated stream-ordered and freed
@@ -345,6 +341,7 @@ int fit_impl(concord_input kind, const void *X, int64_t n64, int64_t p64, double
     const size_t oEdges = cv.take<int>(active ? 2 * (size_t)std::max(ecap, 1ll) : 1);
     const size_t oEcount = cv.take<int>(1);
     const size_t oPart = cv.take<int>(active ? (size_t)Mmax * p : 1);
+    const size_t oColour = cv.take<int>(active ? (size_t)std::max(ecap, 1ll) : 1);
     Workspace ws;
     ws.stream = stream;
     ws.bytes = cv.off;
@@ -422,9 +419,10 @@ int fit_impl(concord_input kind, const void *X, int64_t n64, int64_t p64, double
         CK_HIP(launch_sweep<T>(P, sh.threads, stream));
     } else {
         int *edges = (int *)(B + oEdges), *ecount = (int *)(B + oEcount), *dpart = (int *)(B + oPart);
+        int *dcolour = (int *)(B + oColour);
         T *ompT = (T *)(B + oOmpT), *omdpT = (T *)(B + oOmdpT);
         std::vector<unsigned long long> lred(4 * (size_t)redsw);
-        std::vector<int> hpart;  // partner table of the current colouring (host copy)
+        std::vector<int> hcolour;  // colour of each support edge (host copy)
         int lout[kOutWords];
         // one launch of the sweep kernel from a clean barrier and reduction state
         auto run = [&](int mx) -> int {
@@ -467,9 +465,11 @@ int fit_impl(concord_input kind, const void *X, int64_t n64, int64_t p64, double
                                       hipMemcpyDeviceToHost, stream));
                 CK_HIP(hipStreamSynchronize(stream));
             }
-            const int mt = greedy_colouring(he.data(), ne, p, &hpart);
-            CK_HIP(hipMemcpyAsync(dpart, hpart.data(), sizeof(int) * hpart.size(),
-                                  hipMemcpyHostToDevice, stream));
+            const int mt = greedy_colouring(he.data(), ne, p, &hcolour);
+            if (ne > 0)
+                CK_HIP(hipMemcpyAsync(dcolour, hcolour.data(), sizeof(int) * (size_t)ne,
+                                      hipMemcpyHostToDevice, stream));
+            CK_HIP(launch_partner_table(edges, dcolour, ne, p, mt, dpart, stream));
             CK_HIP(hipStreamSynchronize(stream));
             // the sweep layout of that colouring, from the dense Omega
             CK_HIP(launch_init_omega<T>((const T *)omega, p, sh.Gr, sh.Gc, sh.nr_max, ompT, omdpT,

@@ -32,6 +32,11 @@ hipError_t launch_finalize(const T *omp, const T *omdp, int Gr, int Gc, int NR, 
 template <typename T>
 hipError_t launch_support_edges(const T *omega, int p, int *count, int *edges, long long cap,
                                 hipStream_t st);
+// The m x p partner table of a colouring of the edge list: part[c * p + v] =
+// the partner of v in colour c, -1 where v has none; colour[e] is the colour
+// of edge e = (edges[2 e], edges[2 e + 1]).
+hipError_t launch_partner_table(const int *edges, const int *colour, int ne, int p, int m,
+                                int *part, hipStream_t st);
 template <typename T>
 hipError_t launch_scatter_omega(const T *omp, const T *omdp, const int *part, int mt, int Gr,
                                 int Gc, int NR, int p, T *omega, hipStream_t st);
