@@ -184,12 +184,13 @@ def batched_measurement(plain_all: bool) -> dict:
         if code < 0:
             raise RuntimeError(f"batched solve failed with status {code}")
         last[(None if pw is None else tuple(pw), None if pc is None else tuple(pc), cpl,
-              threads or 512)] = (infos, code)
+              infos[0][0]["block_threads"])] = (infos, code)
         return infos, wall
 
     total = torch.cuda.get_device_properties(0).multi_processor_count
-    # FP32 batch: the wide workgroups hold 1024 threads
-    best = autotune.search(run_batch, [int(x) for x in ps], total, wide_threads=1024, log=log)
+    # FP32 batch: the library's default workgroups are the wide ones, 1024
+    # threads with one row each
+    best = autotune.search(run_batch, [int(x) for x in ps], total, threads=1024, log=log)
     wall_default = best["trials"][0]["wall_s"]
     tuned = best["problem_workgroups"]
     infos, code = last[(tuple(tuned), tuple(best["problem_col_slices"]), best["cols_per_lane"],

@@ -175,8 +175,9 @@ typedef struct {
     /* Threads per workgroup, a multiple of 64: up to 512, each thread holding
      * up to two rows of W; or wide workgroups, up to 1024 in FP32 and 768 in
      * FP64, each thread holding one row (more problems then leave half of
-     * their waves to background rewrites).  0 = 512.  R = rows a workgroup
-     * holds: 2 x block_threads up to 512 threads, block_threads above. */
+     * their waves to background rewrites).  0 = 1024 in FP32, 512 in FP64.
+     * R = rows a workgroup holds: 2 x block_threads up to 512 threads,
+     * block_threads above. */
     int32_t block_threads;
     int32_t pending_depth;  /* 2..8 row updates held before a row is rewritten (0 = 8) */
     int32_t cols_per_lane;  /* columns of W each lane carries in a row rewrite: 2 or 4 (0 = 4) */

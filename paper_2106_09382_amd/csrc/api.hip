@@ -1110,7 +1110,11 @@ int batched_impl(int B, concord_input kind, const void *const *X, const int64_t 
 {
     const int cus = std::max(1, cu_count());
     int total = (o && o->workgroups > 0) ? o->workgroups : cus;
-    int threads = (o && o->block_threads > 0) ? o->block_threads : 512;
+    // default width: wide workgroups in FP32 (they hold as many rows as 512
+    // threads with two rows each, and more problems rewrite in the
+    // background); 512 threads in FP64, whose wide form holds fewer rows
+    int threads = (o && o->block_threads > 0) ? o->block_threads
+                                              : (sizeof(T) == 4 ? wide_threads<T>() : 512);
     int depth = (o && o->pending_depth > 0) ? o->pending_depth : 8;
     const int cpl = (o && o->cols_per_lane > 0) ? o->cols_per_lane : 4;
     if (o && (o->workgroups < 0 || o->block_threads < 0 || o->pending_depth < 0 ||
