@@ -289,9 +289,11 @@ typedef struct {
  *   info       out (host, may be NULL)
  * The launch runs 2 row_groups x col_slices workgroups (by default each
  * population gets half the compute units).  Options (opts may be NULL):
- * row_groups, col_slices, block_threads (at most 512 here), w_in_lds,
- * pending_depth and delta_trace as for concord_fit_ex; active_set, w_out and
- * device_timestamps must be zero (CONCORD_EINVAL otherwise).
+ * row_groups, col_slices, block_threads (wide workgroups here up to 768
+ * threads in both precisions; 0 = 768 with W in HBM when the rows fill at
+ * most half of the waves, else 512), w_in_lds, pending_depth and delta_trace
+ * as for concord_fit_ex; active_set, w_out and device_timestamps must be
+ * zero (CONCORD_EINVAL otherwise).
  * Returns CONCORD_OK, CONCORD_NOT_CONVERGED or a negative code.
  */
 int concord_fit_joint(concord_input kind, const void *X1, const void *X2, int64_t n1, int64_t n2,

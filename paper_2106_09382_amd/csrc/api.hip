@@ -84,11 +84,12 @@ int max_shared_per_block()
 // workgroup; larger ones over a grid of Gr x Gc workgroups, one per CU (of
 // the 1 / cu_share of the CUs the solve gets), with W blocks in LDS when they
 // fit.  Rows of a workgroup are dealt to threads, at most two per thread.
-// wide_ok: the launch may use the wide sweep kernel (workgroups of more than
-// 512 threads, W in HBM); the joint kernel has only the 512-thread form.
+// wide_max: the widest workgroup of the kernel's wide form (more than 512
+// threads, one row per thread, W in HBM): wide_threads<T>() for a single
+// solve, kJointWideThreads for the joint one (cu_share 2).
 template <typename T>
 int choose_shape(int p, const concord_options *o, Shape *sh, int cu_share = 1,
-                 bool wide_ok = true)
+                 int wide_max = wide_threads<T>())
 {
     const int cus = std::max(1, cu_count() / cu_share);
     int Gr = o ? o->row_groups : 0, Gc = o ? o->col_slices : 0;
@@ -99,7 +100,7 @@ int choose_shape(int p, const concord_options *o, Shape *sh, int cu_share = 1,
         depth > 8)
         return CONCORD_EINVAL;
     // more than 512 threads: the wide kernel, W in HBM
-    if (threads > 512 && (!wide_ok || threads > wide_threads<T>() || wl == 1))
+    if (threads > 512 && (threads > wide_max || wl == 1))
         return CONCORD_EINVAL;
     if (Gr == 0 && Gc == 0) {
         if (p <= 96) {
@@ -107,12 +108,13 @@ int choose_shape(int p, const concord_options *o, Shape *sh, int cu_share = 1,
         } else {
             Gc = p < 512 ? 1 : (p < 2048 ? 2 : 8);
             Gr = std::max(1, cus / Gc);
-            // Without wide workgroups (the joint solve): fewer column slices
-            // until a workgroup's rows fill at most half of its waves, so that
-            // the others rewrite rows in the background (two populations at
-            // p = 5000: 32 x 4 per population instead of 16 x 8)
-            const int waves = (threads ? threads : 512) / 64;
-            while (!wide_ok && Gc > 2 && 2 * (((p + Gr - 1) / Gr + 63) / 64) > waves) {
+            // Two populations sharing the CUs (the joint solve): fewer column
+            // slices until a workgroup's rows fill at most half of 512
+            // threads' waves, which leaves most waves of its workgroup to the
+            // background rewrites (p = 5000: 32 x 4 per population instead of
+            // 16 x 8; measured 350 ms against 370 ms, both at 768 threads)
+            const int waves = (threads ? std::min(threads, 512) : 512) / 64;
+            while (cu_share > 1 && Gc > 2 && 2 * (((p + Gr - 1) / Gr + 63) / 64) > waves) {
                 Gc /= 2;
                 Gr = std::max(1, cus / Gc);
             }
@@ -163,8 +165,8 @@ int choose_shape(int p, const concord_options *o, Shape *sh, int cu_share = 1,
         return CONCORD_ELAUNCH;
     // W in HBM: the wide kernel by default when the rows leave at least half
     // of its waves to the background rewrites
-    const int wt = wide_threads<T>();
-    if (auto_threads && wide_ok && !sh->w_lds && Gr * Gc > 1 &&
+    const int wt = wide_max;
+    if (auto_threads && wt > 512 && !sh->w_lds && Gr * Gc > 1 &&
         sh->depth >= 4 && 2 * ((sh->nr_max + 63) / 64) <= wt / 64) {
         sh->threads = wt;
         sh->rpt = 1;
@@ -1202,7 +1204,7 @@ int joint_impl(concord_input kind, const void *const X[2], const int64_t n[2], i
     if (opts && (opts->active_set || opts->w_out || opts->device_timestamps))
         return CONCORD_EINVAL;
     Shape sh;
-    int rc = choose_shape<T>(p, opts, &sh, 2, false);
+    int rc = choose_shape<T>(p, opts, &sh, 2, kJointWideThreads);
     if (rc)
         return rc;
     const Circle C = Circle::make(p);

@@ -26,8 +26,26 @@ __global__ void __launch_bounds__(512) pcd_joint_kernel(SweepParams<T> P0, Sweep
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int G = (int)gridDim.x / 2;
     const int pop = (int)blockIdx.x >= G ? 1 : 0;
-    pcd_solve<T, WLDS, RPT, 2, false, false, true, BG>(pop ? P1 : P0, (int)blockIdx.x - pop * G,
-                                                       G, smem_raw);
+    // both joint kernels instantiate the same solve body for one row per
+    // thread in HBM; inlined in each, as in every other kernel
+    [[clang::always_inline]] pcd_solve<T, WLDS, RPT, 2, false, false, true, BG>(
+        pop ? P1 : P0, (int)blockIdx.x - pop * G, G, smem_raw);
+}
+
+// The same in workgroups of up to kJointWideThreads threads, one row per
+// thread, W in HBM: the waves beyond the rows rewrite in the background.  At
+// 768 threads the kernel holds 168 VGPRs a wave and spills a few more in
+// FP64, which measured cheaper than the five waves the 512-thread kernel
+// leaves to the rewrites.
+template <typename T, int BG>
+__global__ void __launch_bounds__(kJointWideThreads)
+    pcd_joint_wide_kernel(SweepParams<T> P0, SweepParams<T> P1)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int G = (int)gridDim.x / 2;
+    const int pop = (int)blockIdx.x >= G ? 1 : 0;
+    [[clang::always_inline]] pcd_solve<T, false, 1, 2, false, false, true, BG>(
+        pop ? P1 : P0, (int)blockIdx.x - pop * G, G, smem_raw);
 }
 
 template <typename T>
@@ -43,7 +61,12 @@ hipError_t launch_sweep_joint(const SweepParams<T> &P0, const SweepParams<T> &P1
     SweepParams<T> a0 = P0, a1 = P1;
     void *args[] = {&a0, &a1};
     const void *fn;
-    if (P0.w_lds)
+    if (threads > 512) {
+        if (P0.w_lds || P0.rpt > 1 || threads > kJointWideThreads)
+            return hipErrorInvalidValue;
+        fn = P0.ovl ? (const void *)pcd_joint_wide_kernel<T, 1>
+                    : (const void *)pcd_joint_wide_kernel<T, 0>;
+    } else if (P0.w_lds)
         fn = P0.rpt <= 1 ? (const void *)pcd_joint_kernel<T, true, 1, 0>
                          : (const void *)pcd_joint_kernel<T, true, 2, 0>;
     else if (P0.ovl)

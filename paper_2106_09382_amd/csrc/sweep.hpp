@@ -158,6 +158,11 @@ constexpr int wide_threads()
     return sizeof(T) == 4 ? 1024 : 768;
 }
 
+// Widest workgroup of the joint (two-population) kernel, in both precisions:
+// its row state is larger, and 768 threads (168 VGPRs a wave) is the widest
+// at which it spills little.
+constexpr int kJointWideThreads = 768;
+
 // threads > 512 launches the wide kernel, which needs W in HBM, one row per
 // thread and threads <= wide_threads<T>().
 template <typename T>

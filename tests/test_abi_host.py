@@ -155,11 +155,14 @@ def test_wide_workgroups_are_checked_before_device_work(lib, dt, threads, wl, wa
     assert rc == getattr(_lib, want)
 
 
-def test_joint_solve_has_no_wide_workgroups(lib):
+@pytest.mark.parametrize("dt", [0, 1])
+def test_joint_wide_workgroups_stop_at_768_threads(lib, dt):
+    """The joint kernel's wide form reaches 768 threads in both precisions;
+    1024 is refused before any device work."""
     from paper_2106_09382_amd import _lib
     opts = _lib.ConcordOptions()
     opts.block_threads = 1024
-    rc, _ = _fit_joint(lib, opts=opts, dt=0)
+    rc, _ = _fit_joint(lib, opts=opts, dt=dt)
     assert rc == _lib.EINVAL
 
 

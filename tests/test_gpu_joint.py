@@ -94,6 +94,10 @@ CASES = [
     (300, 150, 0.15, 0.05, 16, dict(row_groups=2, col_slices=2, block_threads=128, w_in_lds=2)),
     (160, 200, 0.1, 0.03, 17, dict(row_groups=2, col_slices=2, block_threads=64, w_in_lds=1)),
     (301, 150, 0.2, 0.1, 9, {}),
+    # wide workgroups: one row per thread, W in HBM, rewrites in the background
+    (211, 300, 0.1, 0.02, 8, dict(row_groups=16, col_slices=4, block_threads=768, w_in_lds=2)),
+    (300, 150, 0.15, 0.05, 16, dict(row_groups=4, col_slices=2, block_threads=640, w_in_lds=2,
+                                    pending_depth=5)),
 ]
 
 
