@@ -74,10 +74,15 @@ def cpu_oracle_baseline(S, p: int, lam: float, elem: int, gpu_sweeps: int, bytes
     import oracle
 
     m = p + (p & 1) - 1
-    t0 = time.perf_counter()
-    oracle.pcd(S, lam, 1e-300, 1, colour_limit=2)
-    per = (time.perf_counter() - t0) / 2
-    c = int(max(2, min(m, budget_s / max(per, 1e-9))))
+    # time per colour from two short runs (their difference leaves out the
+    # call's fixed set-up), then as many colours as fill the budget
+    ts = []
+    for cl in (2, 6):
+        t0 = time.perf_counter()
+        oracle.pcd(S, lam, 1e-300, 1, colour_limit=cl)
+        ts.append(time.perf_counter() - t0)
+    per = max((ts[1] - ts[0]) / 4, 1e-9)
+    c = int(max(2, min(m, (budget_s - max(ts[0] - 2 * per, 0.0)) / per)))
     t0 = time.perf_counter()
     oracle.pcd(S, lam, 1e-300, 1, colour_limit=c)
     dt = time.perf_counter() - t0
