@@ -87,7 +87,9 @@ typedef struct {
      * its waves, else 512 (256 for a single workgroup). */
     int32_t block_threads;
     int32_t w_in_lds;       /* -1/0 = auto, 1 = force W blocks in LDS, 2 = force W in HBM */
-    int32_t pending_depth;  /* 0 = auto, else 2..8: updates a row holds before it is rewritten */
+    /* 0 = auto (2 with W in LDS; 8 with W in HBM, 5 in FP32 wide workgroups),
+     * else 2..8: updates a row holds before it is rewritten */
+    int32_t pending_depth;
     double *delta_trace;    /* optional host array of maxit entries: delta of every sweep */
     /* Optional device array of workgroups x timestamp_steps x 3 words: for
      * each of the first timestamp_steps colour steps, thread 0 of every
