@@ -7,7 +7,7 @@
 //   concord_bench --copy MIB
 //   concord_bench --y FILE --y2 FILE2 --lam2 L2 --n N --p P [...]
 //   concord_bench --batched DIR [--plan FILE] [--tol T] [--maxit K] [--reps R]
-//                 [--threads C] [--cpl K] [--sync-rewrites]
+//                 [--threads C] [--cpl K] [--depth D] [--sync-rewrites]
 //   concord_bench --backward --y FILE --n N --p P [--lam L] [--tol T] [--reps R]
 //
 // With both --y and --batched, the single solves run first and then one
@@ -55,7 +55,7 @@ void usage()
                  "[--sync-rewrites]\n"
                  "       concord_bench --copy MIB\n"
                  "       concord_bench --batched DIR [--plan FILE] [--tol T] [--maxit K] "
-                 "[--reps R] [--threads C] [--cpl K]\n"
+                 "[--reps R] [--threads C] [--cpl K] [--depth D]\n"
                  "       concord_bench --backward --y FILE --n N --p P [--lam L] [--tol T] "
                  "[--reps R]\n"
                  "       concord_bench RUN --then RUN [--then RUN ...]\n");
@@ -63,7 +63,7 @@ void usage()
 
 // The batched workload from DIR, FP32, one launch per repetition.
 int run_batched(const std::string &dir, const std::string &plan, double tol, int maxit, int reps,
-                int threads, int cpl, int sync_rw)
+                int threads, int cpl, int sync_rw, int depth)
 {
     std::vector<int64_t> ps, ns;
     {
@@ -145,6 +145,7 @@ int run_batched(const std::string &dir, const std::string &plan, double tol, int
     bo.problem_col_slices = any_slices ? pc.data() : nullptr;
     bo.block_threads = threads;
     bo.cols_per_lane = cpl;
+    bo.pending_depth = depth;
     bo.sync_rewrites = sync_rw;
     std::vector<concord_info> info((size_t)B * L);
     int rc = 0;
@@ -265,7 +266,7 @@ int run(int argc, char **argv)
     }
     if (!bdir.empty() && path.empty())
         return run_batched(bdir, plan, tol, maxit, reps, opt.block_threads, cpl,
-                           opt.sync_rewrites);
+                           opt.sync_rewrites, opt.pending_depth);
     if (path.empty() || n < 1 || p < 1 || reps < 1) {
         usage();
         return 2;
@@ -403,7 +404,7 @@ int run(int argc, char **argv)
         // the batched workload after the single solves, in the same process
         // (one profiler run then covers both kernels), at the batch's own
         // tolerance and sweep limit, one repetition, 512 threads
-        return run_batched(bdir, plan, 1e-5, 500, 1, 0, cpl, opt.sync_rewrites);
+        return run_batched(bdir, plan, 1e-5, 500, 1, 0, cpl, opt.sync_rewrites, 0);
     }
     return rc < 0 ? 1 : 0;
 }
